@@ -1,0 +1,246 @@
+"""Seeded synthetic scenes: geometry, initial conditions and run parameters.
+
+This module is the one input source shared by the oracle and the HIP path.
+It holds none of the method's arithmetic: it places particles on lattices,
+draws seeded random states, and fixes the run parameters of each workload
+(particle spacing, smoothing length h = 1.3 dx and support 2.6 dx as in the
+paper's Sec. 4, sound speed, time step).  Kernel sums, wall pressure, normals,
+reference number density and every other step of the method are computed by
+each side on its own.
+
+Conventions: positions are row-major ``(n, dim)`` float64 arrays, the last
+axis is vertical and gravity points along -e_{dim-1}.  Particles sit on the
+lattice points (i + 1/2) dx (the paper places particles "regularly on a
+Cartesian grid", Secs. 4.1 and 4.3).  Tanks have ``layers`` of wall dummy
+particles on the floor and the side walls and an open top (Fig. 1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+G = 9.81            # gravity used for every case (Sec. 4)
+RHO_WATER = 1000.0  # reference density of water (Secs. 4.1-4.3)
+H_OVER_DX = 1.3     # smoothing length over particle spacing (Sec. 4)
+
+
+@dataclass
+class Scene:
+    name: str
+    dim: int
+    dx: float
+    h: float
+    rho0: float
+    c0: float
+    mu: float
+    gamma_p: float
+    g: np.ndarray            # (3,) body force; unused trailing entries are 0
+    dt: float
+    steps: int
+    H: float                 # initial water depth (hydrostatic reference)
+    fluid_x: np.ndarray      # (Nf, dim)
+    fluid_v: np.ndarray      # (Nf, dim)
+    fluid_rho: np.ndarray    # (Nf,)
+    wall_x: np.ndarray       # (Nw, dim)
+    lo: np.ndarray           # (dim,) lower corner of the cell grid
+    hi: np.ndarray           # (dim,) upper corner of the cell grid
+    penalty_all: bool = True
+    probe: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int64))
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.fluid_x.shape[0])
+
+    @property
+    def n_wall(self) -> int:
+        return int(self.wall_x.shape[0])
+
+    def with_params(self, **kw) -> "Scene":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Scene(**d)
+
+
+def sound_speed(H: float) -> float:
+    """c0 = 10 sqrt(2 g H), the run parameter of every workload here."""
+    return 10.0 * math.sqrt(2.0 * G * H)
+
+
+def time_step(h: float, c0: float) -> float:
+    """Fixed step from the CFL and body-force limits (Eqs. (23)-(24)) with the
+    anticipated maximum velocity c0/10."""
+    return min(0.25 * h / (c0 + 0.1 * c0), 0.25 * math.sqrt(h / G))
+
+
+def _lattice(n, dx, shift=None):
+    """Lattice points (i + 1/2) dx, i in [0, n_k) per axis, x fastest."""
+    axes = [(np.arange(k, dtype=np.float64) + 0.5) * dx for k in n]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")
+    pts = np.stack([g.ravel() for g in grids[::-1]], axis=1)
+    if shift is not None:
+        pts = pts + np.asarray(shift, dtype=np.float64)
+    return pts
+
+
+def tank_walls(dim, n_in, n_top, dx, layers=3):
+    """Wall dummies of an open tank whose interior holds n_in[k] lattice
+    columns per horizontal axis and n_top lattice rows in height.  The walls
+    are ``layers`` lattice rows thick on the floor and the sides."""
+    lo = [-layers] * dim
+    hi = [n + layers for n in n_in] + [n_top]
+    idx = [np.arange(lo[k], hi[k]) for k in range(dim)]
+    grids = np.meshgrid(*idx[::-1], indexing="ij")
+    ijk = np.stack([g.ravel() for g in grids[::-1]], axis=1)
+    inside = np.ones(len(ijk), dtype=bool)
+    for k in range(dim - 1):
+        inside &= (ijk[:, k] >= 0) & (ijk[:, k] < n_in[k])
+    inside &= ijk[:, dim - 1] >= 0
+    ijk = ijk[~inside]
+    return (ijk.astype(np.float64) + 0.5) * dx
+
+
+def _hydrostatic_rho(z, H, rho0, c0):
+    """Initial density whose linear-EOS pressure is rho0 g (H - z)."""
+    return rho0 + rho0 * G * (H - z) / (c0 * c0)
+
+
+def _box(lo, hi):
+    return np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+
+
+def hydrostatic_tank_2d(dx=0.025, H=1.0, L=1.0, top=1.1, mu=1e-3, steps=200):
+    """2-D tank at rest: L x H water on a square lattice, 3 wall layers on the
+    floor and the sides up to ``top``."""
+    nx = int(round(L / dx))
+    nz = int(round(H / dx))
+    fx = _lattice([nx, nz], dx)
+    wx = tank_walls(2, [nx], int(round(top / dx)), dx)
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c0)
+    lo, hi = _box([-3.5 * dx, -3.5 * dx], [L + 3.5 * dx, top + 6 * h])
+    return Scene("hydrostatic_tank_2d", 2, dx, h, RHO_WATER, c0, mu, 1.0,
+                 np.array([0.0, -G, 0.0]), time_step(h, c0), steps, H, fx, np.zeros_like(fx),
+                 rho, wx, lo, hi, meta=dict(L=L, top=top))
+
+
+def _obstacles(dx, seed, count, tank):
+    """Wall dummies of ``count`` seeded spheres/cubes resting on the floor:
+    lattice points inside the union that lie less than 3 dx below its
+    surface.  Shape type 50/50, radius (or cube half-size) ~ U[0.03, 0.08],
+    centre x ~ U[0.7, 1.5], y ~ U[r, W - r], z = r."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 2))
+        r = float(rng.uniform(0.03, 0.08))
+        cx = float(rng.uniform(0.7, 1.5))
+        cy = float(rng.uniform(r, tank[1] - r))
+        shapes.append((kind, r, np.array([cx, cy, r])))
+    nx, ny, nz = (int(round(t / dx)) for t in tank)
+    pts = []
+    for kind, r, c in shapes:
+        lo = np.maximum(np.floor((c - r) / dx - 1).astype(int), 0)
+        hi = np.minimum(np.ceil((c + r) / dx + 1).astype(int), [nx, ny, nz])
+        axes = [np.arange(lo[k], hi[k]) for k in range(3)]
+        g = np.meshgrid(*axes[::-1], indexing="ij")
+        ijk = np.stack([a.ravel() for a in g[::-1]], axis=1)
+        pts.append(ijk)
+    ijk = np.unique(np.concatenate(pts), axis=0)
+    # keep x-fastest generation order
+    order = np.lexsort((ijk[:, 0], ijk[:, 1], ijk[:, 2]))
+    ijk = ijk[order]
+    p = (ijk.astype(np.float64) + 0.5) * dx
+    depth = np.full(len(p), -np.inf)
+    for kind, r, c in shapes:
+        if kind == 0:
+            d = r - np.linalg.norm(p - c, axis=1)
+        else:
+            d = np.min(r - np.abs(p - c), axis=1)
+        depth = np.maximum(depth, d)
+    keep = (depth >= 0.0) & (depth < 3.0 * dx)
+    return p[keep], shapes
+
+
+def dam_break_3d(dx=0.004, obstacles=0, seed=0, mu=1e-3, steps=2000, headroom=0.3):
+    """3-D dam break: a 0.6 (x) x 0.6 (y) x 0.3 (z) m water column in the
+    corner of a 1.6 x 0.6 x 0.6 m tank, 3 wall layers, optional seeded
+    obstacles on the floor."""
+    tank = (1.6, 0.6, 0.6)
+    H = 0.3
+    ntank = [int(round(tank[0] / dx)), int(round(tank[1] / dx))]
+    ncol = [int(round(0.6 / dx)), int(round(0.6 / dx)), int(round(H / dx))]
+    fx = _lattice(ncol, dx)
+    wx = tank_walls(3, ntank, int(round(tank[2] / dx)), dx)
+    meta = dict(tank=tank, column=(0.6, 0.6, H))
+    if obstacles:
+        ox, shapes = _obstacles(dx, seed, obstacles, tank)
+        wx = np.concatenate([wx, ox])
+        meta["obstacles"] = [(k, r, c.tolist()) for k, r, c in shapes]
+        meta["n_obstacle"] = int(len(ox))
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    rho = _hydrostatic_rho(fx[:, 2], H, RHO_WATER, c0)
+    lo, hi = _box([-3.5 * dx] * 3, [tank[0] + 3.5 * dx, tank[1] + 3.5 * dx, tank[2] + headroom])
+    name = "dam_break_3d" + ("_obstacles" if obstacles else "")
+    return Scene(name, 3, dx, h, RHO_WATER, c0, mu, 1.0, np.array([0.0, 0.0, -G]),
+                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi, meta=meta)
+
+
+def dam_break_2d(dx=0.005, mu=1e-3, steps=1000, probe_height=0.1):
+    """2-D dam break: a 1 x 2 m column in a 4 x 3 m tank.  The probe is the
+    innermost layer of the left wall for 0 <= z <= probe_height."""
+    W, Ht = 4.0, 3.0
+    H = 2.0
+    ncol = [int(round(1.0 / dx)), int(round(H / dx))]
+    fx = _lattice(ncol, dx)
+    wx = tank_walls(2, [int(round(W / dx))], int(round(Ht / dx)), dx)
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c0)
+    probe = np.nonzero((np.abs(wx[:, 0] + 0.5 * dx) < 1e-9 * dx + 1e-12) &
+                       (wx[:, 1] > 0.0) & (wx[:, 1] < probe_height))[0]
+    lo, hi = _box([-3.5 * dx, -3.5 * dx], [W + 3.5 * dx, Ht + 0.5])
+    return Scene("dam_break_2d", 2, dx, h, RHO_WATER, c0, mu, 1.0, np.array([0.0, -G, 0.0]),
+                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi,
+                 probe=probe.astype(np.int64))
+
+
+def random_box(dim=3, n=1500, seed=0, dx=0.01, box_cells=None, walls=True, H=0.3, mu=1e-3,
+               vel_scale=0.1, rho_noise=0.005):
+    """Seeded random cloud for stage parity: n fluid particles uniform in a
+    box above a 3-layer floor (or no walls), v ~ N(0, vel_scale sqrt(2gH)),
+    rho = rho0 (1 + N(0, rho_noise))."""
+    rng = np.random.default_rng(seed)
+    side = (n / (1.0 if dim == 3 else 1.0)) ** (1.0 / dim) * dx if box_cells is None else box_cells * dx
+    fx = rng.uniform(0.0, side, size=(n, dim))
+    fv = rng.normal(0.0, vel_scale * math.sqrt(2 * G * H), size=(n, dim))
+    rho = RHO_WATER * (1.0 + rng.normal(0.0, rho_noise, size=n))
+    if walls:
+        nside = int(math.ceil(side / dx))
+        wx = tank_walls(dim, [nside] * (dim - 1), 0, dx)
+        wx = wx[wx[:, dim - 1] < 0.0]
+    else:
+        wx = np.zeros((0, dim))
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    g = np.zeros(3)
+    g[dim - 1] = -G
+    lo = np.full(dim, -3.5 * dx)
+    hi = np.full(dim, side + 3.5 * dx)
+    return Scene(f"random_box_{dim}d_s{seed}", dim, dx, h, RHO_WATER, c0, mu, 1.0, g,
+                 time_step(h, c0), 1, H, fx, fv, rho, wx, lo, hi)
+
+
+def by_name(name: str, **kw) -> Scene:
+    table = {
+        "hydrostatic_tank_2d": hydrostatic_tank_2d,
+        "dam_break_3d": dam_break_3d,
+        "dam_break_3d_obstacles": lambda **k: dam_break_3d(obstacles=8, **k),
+        "dam_break_2d": dam_break_2d,
+        "random_box": random_box,
+    }
+    return table[name](**kw)

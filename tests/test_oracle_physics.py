@@ -1,0 +1,475 @@
+"""Pins of the oracle's physics against closed forms, invariants, worked
+examples and special cases (no GPU).  Each test names what fixes the
+expected value; none re-types the formula under test.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2110_02621_amd import scenes
+
+G = 9.81
+
+
+def golden():
+    out = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split("=")
+            out[k.strip()] = float(v)
+    return out
+
+
+def lattice(dim, n, dx, origin=0.0):
+    ax = (np.arange(n) + 0.5) * dx + origin
+    g = np.meshgrid(*[ax] * dim, indexing="ij")
+    return np.stack([a.ravel() for a in g], axis=1)
+
+
+def interior(pts, dim, n, dx, margin):
+    lo = margin * dx
+    hi = n * dx - margin * dx
+    return np.all((pts > lo) & (pts < hi), axis=1)
+
+
+def P_(orc, dim, dx=0.01, c=30.0, mu=0.0, g=(0, 0, 0), gamma_p=1.0, penalty=True, a_wall=(0, 0, 0)):
+    return orc.params(dim=dim, dx=dx, h=1.3 * dx, rho0=1000.0, c=c, mu=mu, gamma_p=gamma_p,
+                      dt=1e-4, g=g, a_wall=a_wall, penalty_on=penalty)
+
+
+# ------------------------------------------------------------------ Riemann, Eq. (8)
+def test_riemann_equal_states(orc):
+    r = orc.riemann(1000.0, 0.3, 512.0, 1000.0, 0.3, 512.0, 20.0)
+    assert r["pstar"] == pytest.approx(512.0, abs=1e-12)
+    assert r["Ustar"] == pytest.approx(0.3, abs=1e-15)
+
+
+def test_riemann_acoustic_worked_example(orc):
+    # Head-on collision rho = 1000, U_L = 1, U_R = -1, p = 0, c = 10.  The
+    # limiter factor 3 of Sec. 2.2 gives beta = min(3*2, 10) = 6 and
+    # p* = rho^2 beta (U_L - U_R)/(2 rho) = 1000 * 6 * 2 / 2 = 6000.
+    k = golden()["riemann_limiter_factor"]
+    r = orc.riemann(1000.0, 1.0, 0.0, 1000.0, -1.0, 0.0, 10.0)
+    assert r["beta"] == pytest.approx(min(k * 2.0, 10.0))
+    assert r["pstar"] == pytest.approx(6000.0, rel=1e-14)
+    # stronger collision: the limiter saturates at c, the acoustic
+    # (Toro) value rho c dU / 2 = 1000 * 10 * 10 / 2
+    r = orc.riemann(1000.0, 5.0, 0.0, 1000.0, -5.0, 0.0, 10.0)
+    assert r["pstar"] == pytest.approx(50000.0, rel=1e-14)
+    # expansion: no dissipation, p* = density-weighted mean pressure
+    r = orc.riemann(1000.0, -1.0, 100.0, 1000.0, 1.0, 300.0, 10.0)
+    assert r["beta"] == 0.0
+    assert r["pstar"] == pytest.approx(200.0, rel=1e-14)
+    # U* = Ubar + (p_L - p_R)/(2 c rhobar): 100 Pa jump, c = 10, rho = 1000
+    r = orc.riemann(1000.0, 0.0, 100.0, 1000.0, 0.0, 0.0, 10.0)
+    assert r["Ustar"] == pytest.approx(0.005, rel=1e-14)
+
+
+def test_riemann_density_weighting(orc):
+    # Pbar weights each side's pressure by the OTHER side's density: a light
+    # left state takes most of the right pressure.
+    r = orc.riemann(1.0, 0.0, 0.0, 1000.0, 0.0, 1000.0, 10.0)
+    assert r["pstar"] == pytest.approx(1.0 * 1000.0 / 1001.0, rel=1e-14)
+    assert r["Ubar"] == 0.0
+
+
+def test_riemann_mirror_symmetry(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        rl, rr = rng.uniform(900, 1100, 2)
+        ul, ur = rng.normal(0, 2, 2)
+        pl, pr = rng.normal(0, 1e4, 2)
+        a = orc.riemann(rl, ul, pl, rr, ur, pr, 25.0)
+        b = orc.riemann(rr, -ur, pr, rl, -ul, pl, 25.0)   # pair seen from j
+        assert a["pstar"] == pytest.approx(b["pstar"], rel=1e-13, abs=1e-9)
+
+
+# ------------------------------------------------------------------ Eq. (17)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reinit_rest_lattice_and_isolated_particle(orc, dim):
+    dx = 0.01
+    P = P_(orc, dim, dx)
+    n = 12
+    x = lattice(dim, n, dx)
+    sig = orc.sigma(P, x, np.zeros((0, dim)))
+    inner = interior(x, dim, n, dx, 2.7)
+    # interior of a full rest lattice: sigma = sigma0 and rho* = rho0 -> rho0
+    assert np.allclose(sig[inner], P.sigma0, rtol=1e-13)
+    rho = orc.reinit(P, sig, np.full(len(x), 1000.0))
+    assert np.allclose(rho[inner], 1000.0, rtol=1e-13)
+    # isolated particle: sigma = W(0); with rho* = rho0 the max() branch
+    # restores rho0 exactly; with rho* below rho0 sigma/sigma0 it is dropped
+    s1 = orc.sigma(P, x[:1], np.zeros((0, dim)))
+    assert s1[0] == pytest.approx(orc.W(0.0, 1.3 * dx, dim)[0], rel=1e-15)
+    rs = 1000.0 * s1[0] / P.sigma0
+    assert orc.reinit(P, s1, np.array([1000.0]))[0] == pytest.approx(1000.0, rel=1e-14)
+    assert orc.reinit(P, s1, np.array([0.5 * rs]))[0] == pytest.approx(rs, rel=1e-14)
+    # fixed points: rho* = rho_s and rho* = rho0
+    sig_m = np.array([0.9 * P.sigma0])
+    rs = 1000.0 * 0.9
+    assert orc.reinit(P, sig_m, np.array([rs]))[0] == pytest.approx(rs, rel=1e-14)
+    # compressed particle keeps the excess scaled by rho0/rho*
+    out = orc.reinit(P, np.array([P.sigma0]), np.array([1010.0]))[0]
+    assert out == pytest.approx(1000.0 + 10.0 * 1000.0 / 1010.0, rel=1e-14)
+
+
+# ------------------------------------------------------------------ Eq. (12)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wall_pressure_hydrostatic_exact(orc, dim):
+    # Fluid at rest with p_f = rho0 g (H - z_f): the force balance of Eq. (12)
+    # reproduces rho0 g (H - z_w) on every wall particle with a fluid
+    # neighbour (the z_f dependence cancels).  Large c keeps rho_f ~ rho0.
+    dx = 0.02 if dim == 3 else 0.01
+    sc = scenes.hydrostatic_tank_2d(dx=dx, H=0.3, L=0.3, top=0.4) if dim == 2 else \
+        scenes.dam_break_3d(dx=dx)
+    H = sc.H
+    c = 1000.0
+    g = np.zeros(3)
+    g[dim - 1] = -G
+    P = orc.params(dim=dim, dx=dx, h=1.3 * dx, rho0=1000.0, c=c, g=g)
+    z = sc.fluid_x[:, dim - 1]
+    rho = 1000.0 + 1000.0 * G * (H - z) / c ** 2
+    pw = orc.wall_pressure(P, sc.wall_x, sc.fluid_x, rho)
+    cnt, _ = orc.neighbours(dim, 1.3 * dx, sc.wall_x, sc.fluid_x)
+    has = cnt > 0
+    assert has.sum() > 50
+    ref = 1000.0 * G * (H - sc.wall_x[:, dim - 1])
+    assert np.abs(pw[has] - ref[has]).max() < 2e-6 * 1000.0 * G * H
+    assert np.all(pw[~has] == 0.0)
+
+
+def test_wall_pressure_wall_acceleration(orc):
+    # Accelerating the wall with a_w = g removes the hydrostatic term: p_w is
+    # then a kernel-weighted mean of the fluid pressures, between their
+    # extremes; a_w = 2g reverses the correction.
+    dim, dx = 2, 0.01
+    sc = scenes.hydrostatic_tank_2d(dx=dx, H=0.2, L=0.2, top=0.3)
+    rho = sc.fluid_rho
+    base = orc.params(dim=dim, dx=dx, h=1.3 * dx, rho0=1000.0, c=sc.c0, g=(0, -G, 0))
+    acc = orc.params(dim=dim, dx=dx, h=1.3 * dx, rho0=1000.0, c=sc.c0, g=(0, -G, 0), a_wall=(0, -G, 0))
+    acc2 = orc.params(dim=dim, dx=dx, h=1.3 * dx, rho0=1000.0, c=sc.c0, g=(0, -G, 0), a_wall=(0, -2 * G, 0))
+    p0 = orc.wall_pressure(base, sc.wall_x, sc.fluid_x, rho)
+    p1 = orc.wall_pressure(acc, sc.wall_x, sc.fluid_x, rho)
+    p2 = orc.wall_pressure(acc2, sc.wall_x, sc.fluid_x, rho)
+    pf = sc.c0 ** 2 * (rho - 1000.0)
+    has = p1 != 0
+    assert np.all(p1[has] <= pf.max() + 1e-9) and np.all(p1[has] >= pf.min() - 1e-9)
+    assert np.allclose(p2 - p1, -(p0 - p1), atol=1e-9)
+
+
+# ------------------------------------------------------------------ Eq. (16)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_normals_flat_wall(orc, dim):
+    # Flat 3-layer floor: by reflection symmetry the layer next to the fluid
+    # points up, the middle layer cancels, the outer layer points down.
+    dx = 0.01
+    P = P_(orc, dim, dx)
+    n = 24 if dim == 2 else 14
+    lay = []
+    for k in range(3):
+        pts = lattice(dim - 1, n, dx) if dim > 1 else None
+        z = np.full((len(pts), 1), -(k + 0.5) * dx)
+        lay.append(np.concatenate([pts, z], axis=1))
+    wx = np.concatenate(lay)
+    nrm = orc.normals(P, wx)
+    inner_cols = np.all((wx[:, :-1] > 3 * dx) & (wx[:, :-1] < (n - 3) * dx), axis=1)
+    up = np.zeros(dim)
+    up[-1] = 1.0
+    z = wx[:, -1]
+    L0 = inner_cols & np.isclose(z, -0.5 * dx)
+    L1 = inner_cols & np.isclose(z, -1.5 * dx)
+    L2 = inner_cols & np.isclose(z, -2.5 * dx)
+    assert np.allclose(nrm[L0], up, atol=1e-12)
+    assert np.all(nrm[L1] == 0.0)
+    assert np.allclose(nrm[L2], -up, atol=1e-12)
+
+
+# ------------------------------------------------------------------ Eqs. (9)-(10)
+def _cloud(dim, n, seed, dx=0.01):
+    rng = np.random.default_rng(seed)
+    side = n ** (1 / dim) * dx
+    x = rng.uniform(0, side, (n, dim))
+    v = rng.normal(0, 0.5, (n, dim))
+    rho = 1000.0 * (1 + rng.normal(0, 0.01, n))
+    return x, v, rho
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_momentum_antisymmetry_conserves_momentum(orc, dim):
+    # Eq. (10) (and the viscous term) are antisymmetric in i <-> j: without
+    # walls and gravity the total force vanishes.
+    x, v, rho = _cloud(dim, 800, 5)
+    P = P_(orc, dim, mu=0.05)
+    A = orc.momentum(P, x, v, rho, np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    m = 1000.0 * 0.01 ** dim
+    tot = (m * A).sum(0)
+    assert np.abs(tot).max() < 1e-12 * (m * np.abs(A)).sum()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_galilean_invariance(orc, dim):
+    # Adding one velocity to every particle changes neither dv/dt nor
+    # drho/dt (no walls: only velocity differences enter Eqs. (7)-(10)).
+    x, v, rho = _cloud(dim, 600, 6)
+    P = P_(orc, dim, mu=0.05, g=(0, 0, -G) if dim == 3 else (0, -G, 0))
+    none = (np.zeros((0, dim)), np.zeros(0))
+    V = np.full(dim, 3.7)
+    A0 = orc.momentum(P, x, v, rho, *none, np.zeros((0, dim)))
+    A1 = orc.momentum(P, x, v + V, rho, *none, np.zeros((0, dim)))
+    D0 = orc.continuity(P, x, v, rho, *none)
+    D1 = orc.continuity(P, x, v + V, rho, *none)
+    assert np.abs(A1 - A0).max() < 1e-9 * np.abs(A0).max()
+    assert np.abs(D1 - D0).max() < 1e-9 * np.abs(D0).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_continuity_uniform_translation_and_compression(orc, dim):
+    dx = 0.01
+    n = 12
+    x = lattice(dim, n, dx)
+    P = P_(orc, dim, dx)
+    inner = interior(x, dim, n, dx, 2.7)
+    none = (np.zeros((0, dim)), np.zeros(0))
+    rho = np.full(len(x), 1003.0)
+    D = orc.continuity(P, x, np.tile(np.linspace(0.5, 1.5, dim), (len(x), 1)), rho, *none)
+    assert np.abs(D).max() < 1e-10
+    # linear compression v = -kappa (r - r_c): drho/dt = -rho div v = d kappa rho
+    kappa = 2.0
+    v = -kappa * (x - x.mean(0))
+    D = orc.continuity(P, x, v, rho, *none)
+    ratio = D[inner] / (dim * kappa * 1003.0)
+    assert np.all(ratio > 0.95) and np.all(ratio < 1.0)
+    assert np.ptp(ratio) < 1e-10
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_momentum_uniform_and_linear_pressure(orc, dim):
+    dx = 0.01
+    n = 12
+    x = lattice(dim, n, dx)
+    inner = interior(x, dim, n, dx, 2.7)
+    g = np.zeros(3)
+    g[dim - 1] = -G
+    none = (np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    # uniform pressure: the symmetric lattice sums of grad W vanish, A = g
+    P = P_(orc, dim, dx, c=30.0, g=g)
+    A = orc.momentum(P, x, np.zeros_like(x), np.full(len(x), 1010.0), *none)
+    assert np.abs(A[inner] - g[:dim]).max() < 1e-9 * 9000.0 / (1000 * dx)
+    # linear pressure p = b z, no gravity: A ~ -grad p / rho (lattice factor)
+    c = 1000.0
+    P = P_(orc, dim, dx, c=c)
+    b = 5.0e4
+    p = b * x[:, -1]
+    rho = 1000.0 + p / c ** 2
+    A = orc.momentum(P, x, np.zeros_like(x), rho, *none)
+    ratio = A[inner, -1] / (-b / 1000.0)
+    assert np.all(ratio > 0.95) and np.all(ratio < 1.0)
+    assert np.abs(A[inner, :-1]).max() < 1e-6 * b / 1000.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_viscous_term(orc, dim):
+    dx = 0.01
+    n = 12
+    x = lattice(dim, n, dx)
+    inner = interior(x, dim, n, dx, 2.7)
+    none = (np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    rho = np.full(len(x), 1000.0)
+    mu = 0.3
+    P = P_(orc, dim, dx, mu=mu)
+    P0 = P_(orc, dim, dx, mu=0.0)
+    # linear shear v_x = s z: no net viscous force in the interior
+    v = np.zeros_like(x)
+    v[:, 0] = 4.0 * x[:, -1]
+    A = orc.momentum(P, x, v, rho, *none) - orc.momentum(P0, x, v, rho, *none)
+    assert np.abs(A[inner]).max() < 1e-8
+    # quadratic profile v_x = k z^2: (mu/rho) lap v = 2 k mu / rho
+    k = 50.0
+    v[:, 0] = k * x[:, -1] ** 2
+    A = orc.momentum(P, x, v, rho, *none) - orc.momentum(P0, x, v, rho, *none)
+    ratio = A[inner, 0] / (2 * k * mu / 1000.0)
+    assert np.all(ratio > 0.9) and np.all(ratio < 1.1)
+    # linear in mu
+    P2 = P_(orc, dim, dx, mu=2 * mu)
+    A2 = orc.momentum(P2, x, v, rho, *none) - orc.momentum(P0, x, v, rho, *none)
+    assert np.allclose(A2, 2 * A, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ Eqs. (13)-(15)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_penalty_forced_scene(orc, dim):
+    dx = 0.01
+    n = 16 if dim == 2 else 10
+    lay = []
+    for k in range(3):
+        pts = lattice(dim - 1, n, dx)
+        lay.append(np.concatenate([pts, np.full((len(pts), 1), -(k + 0.5) * dx)], axis=1))
+    wx = np.concatenate(lay)
+    Pn = P_(orc, dim, dx)
+    wn = orc.normals(Pn, wx)
+    centre = np.full(dim, (n // 2) * dx)  # lattice column centre of the floor
+    centre[:-1] = ((n // 2) + 0.5) * dx
+    pw = np.full(len(wx), 500.0)
+    rho = np.array([1005.0])
+    v = np.zeros((1, dim))
+
+    def acc(dist, gamma=1.0, on=True):
+        xi = centre.copy()
+        xi[-1] = -0.5 * dx + dist
+        P = P_(orc, dim, dx, gamma_p=gamma, penalty=on)
+        return orc.momentum(P, xi[None, :], v, rho, wx, pw, wn)[0]
+
+    # within dx/2 of the wall particles' plane: a force along +n_w (up)
+    d = acc(0.3 * dx) - acc(0.3 * dx, on=False)
+    assert d[-1] > 0.0 and np.abs(d[:-1]).max() < 1e-9 * d[-1]
+    # beyond dx/2 (delta >= 1): nothing
+    d = acc(0.6 * dx) - acc(0.6 * dx, on=False)
+    assert np.all(d == 0.0)
+    # linear in gamma_p
+    a0 = acc(0.3 * dx, gamma=0.0)
+    assert np.allclose(acc(0.3 * dx, gamma=2.0) - a0, 2 * (acc(0.3 * dx) - a0), rtol=1e-12)
+    # stronger closer to the plane: (1 - delta)^2
+    assert (acc(0.1 * dx) - acc(0.1 * dx, on=False))[-1] > d[-1]
+
+
+# ------------------------------------------------------------------ Sec. 2.6
+@pytest.mark.parametrize("dim", [2, 3])
+def test_free_fall_is_exact(orc, dim):
+    # An isolated particle keeps rho0 through Eq. (17) and feels only g; the
+    # kick-drift-kick scheme integrates constant acceleration exactly.
+    g = np.zeros(3)
+    g[dim - 1] = -G
+    dt = 1e-3
+    P = orc.params(dim=dim, dx=0.01, h=0.013, rho0=1000.0, c=20.0, dt=dt, g=g)
+    x0 = np.full((1, dim), 0.5)
+    v0 = np.full((1, dim), 0.25)
+    st = orc.State(P, x0, v0, np.array([1000.0]), np.zeros((0, dim)))
+    st.step(100)
+    t = 100 * dt
+    ref = x0 + v0 * t + 0.5 * g[:dim] * t * t
+    assert np.abs(st.x - ref).max() < 1e-13
+    assert np.abs(st.v - (v0 + g[:dim] * t)).max() < 1e-13
+    assert st.rho[0] == pytest.approx(1000.0, rel=1e-15)
+
+
+def test_potential_energy_of_paper_tank(orc):
+    # Sec. 4.1: a 1 m wide, 0.5 m deep water layer holds
+    # T_tot = rho g L H^2 / 2 = 1226.25 J (per metre of depth).
+    gv = golden()
+    L, H = gv["two_phase_tank_L"], gv["two_phase_tank_H"]
+    sc = scenes.hydrostatic_tank_2d(dx=0.01, H=H, L=L, top=2 * H)
+    P = orc.params_from_scene(sc)
+    d = orc.diag(P, sc.fluid_x, sc.fluid_v)
+    assert d["Ep"] == pytest.approx(gv["two_phase_tank_total_energy_J"], rel=1e-12)
+    assert d["M"] == pytest.approx(gv["two_phase_tank_rho_water"] * L * H, rel=1e-12)
+    assert d["Ek"] == 0.0
+
+
+@pytest.mark.slow
+def test_hydrostatic_tank_closed_form(orc):
+    # 2-D tank at rest (dx = 0.025, H = 1): after relaxing the lattice to
+    # rest, 200 plain steps keep p within 5 % (L2) of rho0 g (H - z), the
+    # particles stay put and the mass is exact.
+    sc = scenes.hydrostatic_tank_2d()
+    P = orc.params_from_scene(sc)
+    st = orc.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+    st.step(3000, damp=0.03)
+    st.v[:] = 0.0
+    x0 = st.x.copy()
+    M0 = st.diag()["M"]
+    st.step(200)
+    p = sc.c0 ** 2 * (st.rho - sc.rho0)
+    pa = sc.rho0 * G * (sc.H - st.x[:, 1])
+    ep = np.linalg.norm(p - pa) / np.linalg.norm(pa)
+    assert ep < 5e-2
+    assert np.abs(st.x - x0).max() < 0.05 * sc.dx
+    assert st.diag()["M"] == M0
+    assert st.diag()["vmax"] < 0.01 * math.sqrt(2 * G * sc.H)
+
+
+# ------------------------------------------------------------------ density weighting
+@pytest.mark.parametrize("dim", [2, 3])
+def test_continuity_density_weighted_mean_velocity(orc, dim):
+    # Eq. (9) takes velocities through the density-weighted mean
+    # (rho_i v_i + rho_j v_j)/(rho_i + rho_j): for a centre particle of
+    # density rho_c among neighbours of density rho_n, the velocity part of
+    # drho/dt scales by 2 rho_c/(rho_c + rho_n) against a uniform lattice.
+    dx, n = 0.01, 9
+    x = lattice(dim, n, dx)
+    centre = int(np.argmin(((x - x.mean(0)) ** 2).sum(1)))
+    P = P_(orc, dim, dx, c=40.0)
+    none = (np.zeros((0, dim)), np.zeros(0))
+    v = -2.0 * (x - x.mean(0))
+
+    def vel_part(rho_c):
+        rho = np.full(len(x), 1000.0)
+        rho[centre] = rho_c
+        return (orc.continuity(P, x, v, rho, *none) - orc.continuity(P, x, 0 * v, rho, *none))[centre]
+
+    assert vel_part(2000.0) / vel_part(1000.0) == pytest.approx(2 * 2000.0 / 3000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wall_pressure_scales_with_density(orc, dim):
+    # Dimensional homogeneity of Eq. (12): scaling every density (and rho0)
+    # by lambda at fixed c scales every wall pressure by lambda.
+    sc = scenes.random_box(dim=dim, n=400, seed=2, dx=0.01)
+    P1 = orc.params(dim=dim, dx=0.01, h=0.013, rho0=1000.0, c=sc.c0, g=sc.g)
+    P2 = orc.params(dim=dim, dx=0.01, h=0.013, rho0=2500.0, c=sc.c0, g=sc.g)
+    p1 = orc.wall_pressure(P1, sc.wall_x, sc.fluid_x, sc.fluid_rho)
+    p2 = orc.wall_pressure(P2, sc.wall_x, sc.fluid_x, 2.5 * sc.fluid_rho)
+    assert np.abs(p1).max() > 100.0
+    assert np.allclose(p2, 2.5 * p1, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wall_dummy_acts_like_fluid_at_rest(orc, dim):
+    # Sec. 2.3: dummies enter Eqs. (9)-(10) like fluid particles.  For states
+    # at rest the wall p* of Eq. (11) equals the fluid Riemann p* of Eq. (8),
+    # so a dummy of pressure p_w (density from the EOS) and a fluid particle
+    # of the same density at the same place give the same dv/dt and drho/dt.
+    rng = np.random.default_rng(11)
+    c = 5.0  # small c: wall and fluid densities differ strongly
+    P = P_(orc, dim, 0.01, c=c, penalty=False, g=(0, 0, 0))
+    n = 60
+    x = rng.uniform(0, 0.04, (n, dim))
+    rho = 1000.0 * (1 + rng.uniform(-0.05, 0.3, n))
+    wx = rng.uniform(0, 0.04, (25, dim))
+    pw = rng.uniform(-500.0, 8000.0, 25)
+    wn = np.zeros((25, dim))
+    v0 = np.zeros((n, dim))
+    A_w = orc.momentum(P, x, v0, rho, wx, pw, wn)
+    D_w = orc.continuity(P, x, v0, rho, wx, pw)
+    xa = np.concatenate([x, wx])
+    rho_a = np.concatenate([rho, 1000.0 + pw / c ** 2])
+    none = (np.zeros((0, dim)), np.zeros(0))
+    A_f = orc.momentum(P, xa, np.zeros_like(xa), rho_a, *none, np.zeros((0, dim)))[:n]
+    D_f = orc.continuity(P, xa, np.zeros_like(xa), rho_a, *none)[:n]
+    assert np.allclose(A_w, A_f, rtol=1e-11, atol=1e-9 * np.abs(A_f).max())
+    assert np.allclose(D_w, D_f, rtol=1e-11, atol=1e-9 * np.abs(D_f).max())
+
+
+def test_penalty_lambda_is_quadratic(orc):
+    # Eq. (14): lambda = (1 - delta)^2 with delta = 2 x/dx (Eq. (15)).  At a
+    # fixed geometry (h, positions, normals) only dx changes delta and the
+    # mass; the penalty force per unit mass then follows (1 - delta)^2.
+    dim = 2
+    h = 0.013
+    wx = np.stack([np.arange(-6, 7) * 0.01, np.full(13, -0.005)], axis=1)
+    wn = np.tile([0.0, 1.0], (13, 1))
+    pw = np.full(13, 300.0)
+    xi = np.array([[0.0, -0.005 + 0.002]])
+    v = np.zeros((1, 2))
+    rho = np.array([1004.0])
+
+    def pen(dx):
+        kw = dict(dim=dim, dx=dx, h=h, rho0=1000.0, c=20.0)
+        on = orc.momentum(orc.params(**kw, penalty_on=True), xi, v, rho, wx, pw, wn)[0]
+        off = orc.momentum(orc.params(**kw, penalty_on=False), xi, v, rho, wx, pw, wn)[0]
+        return (on - off)[1] / (1000.0 * dx * dx)
+
+    d1, d2 = 2 * 0.002 / 0.01, 2 * 0.002 / 0.006
+    assert pen(0.01) / pen(0.006) == pytest.approx(((1 - d1) / (1 - d2)) ** 2, rel=1e-12)
