@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the WCSPH step on one MI355X: particle-steps/s of the 3-D
+dam break with seeded obstacles (dx = 0.0025 m: 6.91M fluid + 1.90M wall
+dummy particles), FP32, with the FP64 build of the same kernels timed
+beside it and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  One step = density/reinit + kick/drift, cell sort,
+wall pressure, continuity, momentum + kick: every row of the hot path.
+Inputs are resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (3-D dam break, 4M particles, FP32 vs FP64) + adjoint/fwd ratio"
+
+# Useful (algorithmic) flops per interacting pair of each sweep in 3-D,
+# counted operation by operation from the kernels' formulas (distance from
+# cell + offset, kernel value or gradient, Riemann terms, accumulation);
+# square root, reciprocal and reciprocal square root count as one each.
+# Culled candidates (r >= 2h) are not counted.
+FLOPS_PAIR = {
+    "density": 22,        # sigma += W(r)
+    "wall_bc": 33,        # sum W, sum p W, sum rho r W
+    "continuity_ff": 39,  # Eq. (9) with the Riemann intermediate velocity
+    "continuity_fw": 36,
+    "momentum_ff": 68,    # Eq. (10) with p* of Eq. (8), viscous term
+    "momentum_fw": 64,    # Eq. (11) p*, viscous, penalty test
+}
+# Compulsory HBM bytes per fluid particle of the cell sort in FP32
+# (histogram 16, placement 16, in-cell ordering 8, gather 76) and per cell
+# (count fill, scan read/write, cell table reads): see the design notes.
+SORT_BYTES_PARTICLE = 116
+SORT_BYTES_CELL = 24
+
+PEAK_FP32 = 157.3e12      # MI355X published FP32 vector peak (packed FMA)
+PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, one FMA per lane per clock
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dx", type=float, default=0.0025, help="particle spacing of the dam break")
+    ap.add_argument("--obstacles", type=int, default=8)
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def timed_run(solver_mod, scene, precision, steps, warmup):
+    """Warm up, then time `steps` steps stage by stage with events on the
+    stream the kernels run on.  Returns wall seconds and mean ms per stage."""
+    import torch
+    S = solver_mod.Solver(scene, precision)
+    S.step(warmup)
+    torch.cuda.synchronize()
+    names = ["density", "sort", "wall_bc", "continuity", "momentum"]
+    calls = [S.density, S.build_cells, S.wall_bc, S.continuity, S.momentum]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        e[0].record()
+        for j, fn in enumerate(calls):
+            fn()
+            e[j + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = {n: sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps
+                for j, n in enumerate(names)}
+    return S, wall, stage_ms
+
+
+def pair_counts(S):
+    """Interacting pairs of the current state: fluid-fluid (self excluded),
+    fluid-wall, wall-fluid, and fluid-(fluid+wall) with self."""
+    import torch
+    nf = S.scene.n_fluid
+    cnt, off, lst = S.neighbours(0)
+    lst_t = torch.as_tensor(lst)
+    fw = int((lst_t >= nf).sum())
+    total = int(cnt.astype("int64").sum())
+    ff = total - fw - nf
+    wcnt, _, _ = S.neighbours(1)
+    del lst, lst_t
+    return dict(ff=ff, fw=fw, wf=int(wcnt.astype("int64").sum()), all_with_self=total)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the hot path here is "
+              "the single-GPU sweep; multi-GPU sharding is design-only.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2110_02621_amd import scenes, solver
+
+    sc = scenes.dam_break_3d(dx=args.dx, obstacles=args.obstacles, seed=0, steps=args.steps)
+    nf, nw = sc.n_fluid, sc.n_wall
+    n_tot = nf + nw
+    print(f"[bench] workload dam_break_3d dx={args.dx} obstacles={args.obstacles}: "
+          f"{nf} fluid + {nw} wall", file=sys.stderr, flush=True)
+
+    S, wall, stage = timed_run(solver, sc, "f32", args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    value = n_tot * args.steps / wall
+    st = S.status()
+    pc = pair_counts(S)
+    print(f"[bench] f32 {ms_step:.3f} ms/step  stages {stage}  pairs {pc}  status {st}",
+          file=sys.stderr, flush=True)
+
+    flops = {
+        "density": FLOPS_PAIR["density"] * (pc["all_with_self"]),
+        "wall_bc": FLOPS_PAIR["wall_bc"] * pc["wf"],
+        "continuity": FLOPS_PAIR["continuity_ff"] * pc["ff"] + FLOPS_PAIR["continuity_fw"] * pc["fw"],
+        "momentum": FLOPS_PAIR["momentum_ff"] * pc["ff"] + FLOPS_PAIR["momentum_fw"] * pc["fw"],
+    }
+    kernels = {}
+    for k, f in flops.items():
+        t = stage[k] * 1e-3
+        kernels[k] = dict(ms=round(stage[k], 4), tflops=round(f / t / 1e12, 3),
+                          alu_frac=round(f / t / PEAK_FP32, 4))
+    sort_bytes = SORT_BYTES_PARTICLE * nf + SORT_BYTES_CELL * int(S.desc.n_cells)
+    kernels["sort"] = dict(ms=round(stage["sort"], 4),
+                           gbps=round(sort_bytes / (stage["sort"] * 1e-3) / 1e9, 1),
+                           hbm_frac=round(sort_bytes / (stage["sort"] * 1e-3) / PEAK_HBM, 4))
+    dom = max(("density", "wall_bc", "continuity", "momentum"), key=lambda k: stage[k])
+    ach = flops[dom] / (stage[dom] * 1e-3)
+    roofline = dict(bound="alu", achieved=round(ach / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                    frac=round(ach / PEAK_FP32, 4), traffic=None, kernel=dom)
+    del S
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not args.no_fp64:
+        k64 = args.fp64_steps or args.steps
+        S64, wall64, stage64 = timed_run(solver, sc, "f64", k64, max(2, args.warmup // 2))
+        fp64 = dict(value=n_tot * k64 / wall64, ms_per_step=1e3 * wall64 / k64, steps=k64,
+                    stage_ms={k: round(v, 4) for k, v in stage64.items()})
+        print(f"[bench] f64 {fp64['ms_per_step']:.3f} ms/step stages {stage64}", file=sys.stderr, flush=True)
+        del S64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        P = oracle.params_from_scene(sc)
+        t0 = time.perf_counter()
+        ost = oracle.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+        tinit = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ost.step(args.cpu_steps)
+        tcpu = time.perf_counter() - t0
+        cpu = dict(value=n_tot * args.cpu_steps / tcpu, unit="particle-steps/s", cores=oracle.num_threads(),
+                   kind="oracle",
+                   sample=f"{args.cpu_steps} FP64 oracle step(s) of the full workload "
+                          f"({n_tot} particles), {tcpu:.1f} s (+{tinit:.1f} s initialisation, untimed)")
+        print(f"[bench] cpu oracle {tcpu:.1f} s for {args.cpu_steps} step(s)", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3-D dam break with 8 seeded obstacles, dx={args.dx} m, "
+                               f"{nf} fluid + {nw} wall dummy particles",
+                   "n_fluid": nf, "n_wall": nw, "dx": args.dx, "obstacles": args.obstacles,
+                   "parallelism": "single GPU"},
+        "fluid_particle_steps_per_s": nf * args.steps / wall,
+        "fp64": fp64,
+        "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
+        "adjoint_fwd_ratio": None,
+        "roofline": roofline,
+        "roofline_frac_unpacked_fp32": round(ach / PEAK_FP32_UNPACKED, 4),
+        "kernels": kernels,
+        "pairs": pc,
+        "status": st,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

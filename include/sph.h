@@ -1,0 +1,237 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) weakly-compressible SPH hot path with
+ * the dummy-particle wall treatment of Rezavand, Zhang & Hu, "Generalised
+ * and efficient wall boundary condition treatment in GPU-accelerated SPH"
+ * (arXiv 2110.02621).
+ *
+ * The library follows the paper's statement of the problem (Sec. 3): fluid
+ * particles and fixed wall dummy particles live in device memory for the
+ * whole run and are advanced by the paper's compartments -- neighbour search
+ * with sorting, density update, wall ("BC") pressure, mass and momentum
+ * conservation, time integration -- each one a HIP kernel.  Nothing is
+ * copied to the host by these calls.
+ *
+ * Conventions
+ *   - Every pointer inside sph_buffers and every array argument marked
+ *     "device" is a device pointer owned by the caller.  The library never
+ *     allocates, frees or keeps a pointer between calls, and holds no
+ *     global state.  Scratch memory is passed in (sph_scratch_bytes).
+ *   - T is float when desc->precision == SPH_F32 and double for SPH_F64;
+ *     "T[dim][n]" means dim arrays of n values of T, one after the other
+ *     (structure of arrays: component k of particle i at index k*n + i).
+ *   - Positions are held as an integer cell (linear key) plus an in-cell
+ *     offset in [0, L_c) of type T; the absolute position is
+ *     lo + cell * L_c + offset.
+ *   - "stream" is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work and return; data-dependent faults are counted in the
+ *     device status words, to be read after synchronising.
+ *   - Return codes are synchronous argument, configuration or launch errors
+ *     (SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH).  No call
+ *     aborts or prints.
+ *
+ * Per-step schedule (sph_step runs exactly this):
+ *   sph_density -> sph_build_cells -> sph_wall_bc -> sph_forces(CONTINUITY)
+ *   -> sph_forces(MOMENTUM).
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_OK 0
+#define SPH_ERR_ARG 1    /* null pointer, negative size, size mismatch, bad flag */
+#define SPH_ERR_CONFIG 2 /* dim not 2 or 3, precision unknown, dt above the CFL bound of
+                            Eqs. (23)-(24), grid too large, L_c < 2h */
+#define SPH_ERR_LAUNCH 3 /* a kernel launch failed (hipGetLastError after the launch) */
+
+#define SPH_F32 0
+#define SPH_F64 1
+
+#define SPH_CONTINUITY 1u /* sph_forces: mass conservation, Eq. (9), + density update, Eq. (21) */
+#define SPH_MOMENTUM 2u   /* sph_forces: momentum, Eqs. (10)-(11), (13), + second kick, Eq. (22) */
+#define SPH_NO_KICK 4u    /* with SPH_MOMENTUM: write dv/dt only (initial acceleration) */
+
+/* Device status words (uint32_t[SPH_STATUS_LEN]), counted atomically. */
+#define SPH_STATUS_OUT_OF_GRID 0 /* particle steps whose drift left the cell grid (clamped) */
+#define SPH_STATUS_FAST 1        /* drifts longer than one cell per step (CFL violated) */
+#define SPH_STATUS_NONFINITE 2   /* non-finite values met by sph_diag */
+#define SPH_STATUS_LEN 4
+
+/* Diagnostics written by sph_diag (double[SPH_DIAG_LEN], device). */
+#define SPH_DIAG_MASS 0     /* sum m */
+#define SPH_DIAG_MOM 1      /* sum m v, 3 entries (unused trailing ones 0) */
+#define SPH_DIAG_EKIN 4     /* sum m |v|^2 / 2 */
+#define SPH_DIAG_EPOT 5     /* -sum m g . r */
+#define SPH_DIAG_VMAX 6     /* max |v| */
+#define SPH_DIAG_PROBE 7    /* probe integral J = sum over steps of dt * mean(p_w over probe) */
+#define SPH_DIAG_STEPS 8    /* steps taken since sph_init (as a double) */
+#define SPH_DIAG_LEN 16
+
+/* Run description.  Passed by pointer, read only, except that
+ * sph_configure fills the derived fields (cell .. n_cells). */
+typedef struct sph_desc {
+    int32_t dim;         /* 2 or 3; the last axis is vertical */
+    int32_t precision;   /* SPH_F32 or SPH_F64 */
+    int32_t penalty_all; /* 1: the penalty force of Eq. (13) acts on every fluid-wall pair;
+                            0: no penalty (the paper applies it to the light phase only) */
+    int32_t reserved;
+    double dx;           /* initial particle spacing (enters m = rho0 dx^d and Eq. (15)) */
+    double h;            /* smoothing length; kernel support 2h (Sec. 4: h = 1.3 dx) */
+    double rho0;         /* reference density, Eq. (3) */
+    double c0;           /* artificial sound speed, Eq. (3) */
+    double mu;           /* dynamic viscosity (0: inviscid) */
+    double gamma_p;      /* penalty strength, Eq. (13) (paper: 1) */
+    double dt;           /* time step */
+    double g[3];         /* body force */
+    double a_wall[3];    /* wall acceleration in Eq. (12) */
+    double lo[3];        /* lower corner of the cell grid */
+    double hi[3];        /* upper corner of the cell grid */
+    /* derived by sph_configure: */
+    double cell;         /* cell edge L_c = 2h, rounded to T */
+    double sigma0;       /* reference number density of Eq. (17): full lattice sum */
+    int32_t grid[3];     /* cells per axis (grid[2] = 1 in 2-D) */
+    int32_t reserved2;
+    int64_t n_cells;     /* grid[0] * grid[1] * grid[2] */
+} sph_desc;
+
+/* Device buffers (all caller-owned).  The double-buffered fluid fields have
+ * two copies [0] and [1]; sel_vel / sel_rho name the copy that holds the
+ * current v and rho - rho0 and are updated by the calls that swap them. */
+typedef struct sph_buffers {
+    int64_t n_fluid;
+    int64_t n_wall;
+    /* fluid, length n_fluid unless stated */
+    int32_t *key[2];  /* linear cell key; [0] = sorted state, [1] = drifted, unsorted */
+    int32_t *pid[2];  /* particle id (index in the initial arrays) */
+    void *off[2];     /* T[dim][n_fluid] in-cell offsets */
+    void *vel[2];     /* T[dim][n_fluid] velocity */
+    void *rho[2];     /* T[n_fluid] density minus rho0 */
+    void *acc;        /* T[dim][n_fluid] dv/dt of the last momentum sweep */
+    int32_t sel_vel;  /* copy holding the current velocity (0 or 1) */
+    int32_t sel_rho;  /* copy holding the current density (0 or 1) */
+    /* walls, length n_wall, sorted by cell once by sph_init */
+    int32_t *wkey;
+    int32_t *wpid;    /* wall id (index in the initial wall array) */
+    void *woff;       /* T[dim][n_wall] */
+    void *pw;         /* T[n_wall] wall pressure, Eq. (12) */
+    void *nrm;        /* T[dim][n_wall] wall normal estimate, Eq. (16) */
+    /* cell tables, n_cells + 1 entries: particles of cell k are
+       [start[k], start[k+1]) of the sorted arrays */
+    int32_t *fstart;
+    int32_t *wstart;
+    void *scratch;         /* >= sph_scratch_bytes(...) bytes, 256-byte aligned */
+    size_t scratch_bytes;
+    uint32_t *status;      /* uint32_t[SPH_STATUS_LEN] */
+    double *diag;          /* double[SPH_DIAG_LEN] */
+    void *sigma_out;       /* optional T[n_fluid]: sph_density writes sigma_i (sorted order) */
+    const int32_t *probe;  /* optional: wall ids of the probe patch (device) */
+    int32_t n_probe;
+    int32_t reserved;
+} sph_buffers;
+
+/* Validates the run description and fills its derived fields: L_c = 2h
+ * (rounded to T), the grid covering [lo, hi], and sigma0, the number
+ * density sum_j W of a full square/cubic lattice of spacing dx (the initial
+ * reference value of Eq. (17)).  Host only.  SPH_ERR_CONFIG for dim not in
+ * {2, 3}, unknown precision, h <= 0, dx <= 0, c0 <= 0, hi <= lo, more than
+ * 2^31 - 2 cells, or dt above min(0.25 h/(1.1 c0), 0.25 sqrt(h/|g|))
+ * (Eqs. (23)-(24) with the anticipated maximum velocity c0/10). */
+int sph_configure(sph_desc *desc);
+
+/* Bytes of scratch the calls need for n_fluid fluid and n_wall wall
+ * particles (cell counts, sort keys and permutation, reduction partials). */
+size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
+
+/* Loads the initial state and prepares the run (Sec. 3: the data is copied
+ * to the device once, at the start).
+ *   fpos, fvel  device double[dim][n_fluid]  absolute positions, velocities
+ *   frho        device double[n_fluid]       densities
+ *   wpos        device double[dim][n_wall]   wall dummy positions
+ * Converts positions to cell + offset, sorts walls by cell (once: they are
+ * fixed, Sec. 2.3) and estimates their normals by Eq. (16), sorts the fluid
+ * (sph_build_cells), computes the initial wall pressure (Eq. (12)) and
+ * dv/dt (Eq. (10)), and zeroes status and diag.  Particles outside
+ * [lo, hi] are clamped into the grid and counted in SPH_STATUS_OUT_OF_GRID.
+ * Sets sel_vel and sel_rho. */
+int sph_init(const sph_desc *desc, sph_buffers *buf, const double *fpos, const double *fvel,
+             const double *frho, const double *wpos, void *stream);
+
+/* Neighbour search, "including sorting algorithms" (Sec. 3, Table 1).
+ * Stable counting sort of the drifted fluid (key[1], off[1], pid[1] and the
+ * current velocity and density) by cell key into key[0], off[0], pid[0] and
+ * the other velocity/density copy; particles of one cell keep their prior
+ * order.  Rebuilds fstart.  Swaps sel_vel and sel_rho. */
+int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
+
+/* Density update (Sec. 2.5 and 2.6): at the current positions
+ * sigma_i = sum_{j in fluid and walls} W_ij (j = i included), the
+ * reinitialised density of Eq. (17) with rho* the current density, then
+ * the half kick of Eq. (19) with the stored dv/dt and the drift of Eq. (20).
+ * Writes the new density and the half-step velocity in place (current
+ * copies) and the drifted positions to key[1], off[1], pid[1]. */
+int sph_density(const sph_desc *desc, sph_buffers *buf, void *stream);
+
+/* Wall dummy pressure by force balance with the fluid, Eq. (12), for every
+ * wall particle from the current fluid positions and densities:
+ * p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf] / sum_f W_wf,
+ * 0 when no fluid particle is within 2h.  If a probe is set, adds
+ * dt * mean(p_w over the probe) to diag[SPH_DIAG_PROBE]. */
+int sph_wall_bc(const sph_desc *desc, sph_buffers *buf, void *stream);
+
+/* Pair sweeps over fluid and wall neighbours.
+ * SPH_CONTINUITY: drho_i/dt of Eq. (9) with the Riemann intermediate
+ *   velocity of Eqs. (7)-(8) (walls: v = 0, p = p_w, rho from the EOS),
+ *   then rho^{n+1} = rho + dt drho/dt (Eq. (21)) into the other density
+ *   copy; swaps sel_rho.
+ * SPH_MOMENTUM: dv_i/dt of Eq. (10) with p* of Eq. (8) (fluid) and
+ *   Eq. (11) (walls), the viscous term, the penalty force of Eqs. (13)-(15)
+ *   if penalty_all, and g; stores it in acc and, unless SPH_NO_KICK, the
+ *   velocity of Eq. (22) into the other velocity copy; swaps sel_vel.
+ * Exactly one of the two may be given per call. */
+int sph_forces(const sph_desc *desc, sph_buffers *buf, unsigned which, void *stream);
+
+/* nsteps full time steps (the schedule at the top of this file). */
+int sph_step(const sph_desc *desc, sph_buffers *buf, int nsteps, void *stream);
+
+/* FP64 global reductions into diag (mass, momentum, energies, max |v|;
+ * deterministic order).  Non-finite values are counted in
+ * SPH_STATUS_NONFINITE.  The probe entry and the step count are kept. */
+int sph_diag(const sph_desc *desc, sph_buffers *buf, void *stream);
+
+/* Copies the fluid state out in particle-id order as doubles (device
+ * arrays, any may be NULL): pos double[dim][n_fluid] absolute positions,
+ * vel double[dim][n_fluid], rho double[n_fluid] (full density),
+ * acc double[dim][n_fluid]. */
+int sph_export(const sph_desc *desc, const sph_buffers *buf, double *pos, double *vel,
+               double *rho, double *acc, void *stream);
+
+/* Copies wall pressure (double[n_wall]), normals (double[dim][n_wall]) and
+ * absolute positions as held (double[dim][n_wall]) out in wall-id order
+ * (device arrays, any may be NULL). */
+int sph_export_walls(const sph_desc *desc, const sph_buffers *buf, double *pw, double *nrm,
+                     double *pos, void *stream);
+
+/* Neighbour sets as the sweeps enumerate them (pairs with |r_ij|^2 < 4h^2
+ * computed from cell + offset in T).  which = 0: for every fluid particle
+ * its fluid and wall neighbours, itself included; which = 1: for every wall
+ * particle its fluid neighbours.  count (device int32[n_query], indexed by
+ * particle/wall id) is always written; if list is not NULL, neighbour ids
+ * are written at list[offset[id] ...] (device, offset int64[n_query], the
+ * exclusive prefix sum of count) with walls encoded as n_fluid + wall id;
+ * entries that would fall outside [0, list_len) are dropped. */
+int sph_neighbours(const sph_desc *desc, const sph_buffers *buf, int which, const int64_t *offset,
+                   int32_t *count, int32_t *list, int64_t list_len, void *stream);
+
+/* Static text for a return code. */
+const char *sph_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -59,15 +59,16 @@ def lib():
                                            C.c_double, C.c_double, C.POINTER(C.c_uint8)]
         L.orc_riemann.argtypes = [C.c_double] * 7 + [dp]
         L.orc_riemann.restype = None
-        L.orc_sigma.argtypes = [pp, i64, dp, i64, dp, dp]
+        qp = C.POINTER(C.c_int64)
+        L.orc_sigma.argtypes = [pp, i64, dp, i64, dp, i64, qp, dp]
         L.orc_reinit.argtypes = [pp, i64, dp, dp, dp]
         L.orc_reinit.restype = None
         L.orc_sigma0.argtypes = [C.c_int, C.c_double, C.c_double]
         L.orc_sigma0.restype = C.c_double
-        L.orc_wall_pressure.argtypes = [pp, i64, dp, i64, dp, dp, dp]
+        L.orc_wall_pressure.argtypes = [pp, i64, dp, i64, dp, dp, i64, qp, dp]
         L.orc_normals.argtypes = [pp, i64, dp, dp, dp]
-        L.orc_continuity.argtypes = [pp, i64, dp, dp, dp, i64, dp, dp, dp]
-        L.orc_momentum.argtypes = [pp, i64, dp, dp, dp, i64, dp, dp, dp, dp]
+        L.orc_continuity.argtypes = [pp, i64, dp, dp, dp, i64, dp, dp, i64, qp, dp]
+        L.orc_momentum.argtypes = [pp, i64, dp, dp, dp, i64, dp, dp, dp, i64, qp, dp]
         L.orc_diag.argtypes = [pp, i64, dp, dp, dp]
         L.orc_diag.restype = None
         L.orc_step.argtypes = [pp, i64, dp, dp, dp, dp, i64, dp, dp, dp, C.c_int, ip, C.c_int,
@@ -187,12 +188,25 @@ def riemann(rhoL, UL, pL, rhoR, UR, pR, c):
     return dict(Ustar=out[0], pstar=out[1], Ubar=out[2], Pbar=out[3], beta=out[4])
 
 
-def sigma(P, fx, wx):
+def _query(query, n):
+    """(count, pointer, keep-alive array) of an optional index subset."""
+    if query is None:
+        return n, None, None
+    q = np.ascontiguousarray(query, dtype=np.int64)
+    if len(q) and (q.min() < 0 or q.max() >= n):
+        raise IndexError("query index out of range")
+    return len(q), q.ctypes.data_as(C.POINTER(C.c_int64)), q
+
+
+def sigma(P, fx, wx, query=None):
+    """sigma_i = sum_j W_ij over fluid and walls (j = i included); query
+    selects the fluid particles to evaluate (default all)."""
     fx = _f64(fx, P.dim)
     wx = _f64(wx, P.dim)
-    out = np.zeros(max(len(fx), 1))
-    _check(lib().orc_sigma(C.byref(P), len(fx), _d(fx), len(wx), _d(wx), _d(out)), "sigma")
-    return out[: len(fx)]
+    nq, qp, _keep = _query(query, len(fx))
+    out = np.zeros(max(nq, 1))
+    _check(lib().orc_sigma(C.byref(P), len(fx), _d(fx), len(wx), _d(wx), nq, qp, _d(out)), "sigma")
+    return out[:nq]
 
 
 def reinit(P, sig, rho_star):
@@ -203,14 +217,16 @@ def reinit(P, sig, rho_star):
     return out[: len(sig)]
 
 
-def wall_pressure(P, wx, fx, frho):
+def wall_pressure(P, wx, fx, frho, query=None):
+    """Eq. (12) for every wall particle (or the query subset)."""
     wx = _f64(wx, P.dim)
     fx = _f64(fx, P.dim)
     frho = _f64(frho)
-    out = np.zeros(max(len(wx), 1))
+    nq, qp, _keep = _query(query, len(wx))
+    out = np.zeros(max(nq, 1))
     _check(lib().orc_wall_pressure(C.byref(P), len(wx), _d(wx), len(fx), _d(fx), _d(frho),
-                                   _d(out)), "wall_pressure")
-    return out[: len(wx)]
+                                   nq, qp, _d(out)), "wall_pressure")
+    return out[:nq]
 
 
 def normals(P, wx, with_psi=False):
@@ -223,29 +239,33 @@ def normals(P, wx, with_psi=False):
     return n[: len(wx)]
 
 
-def continuity(P, fx, fv, frho, wx, pw):
+def continuity(P, fx, fv, frho, wx, pw, query=None):
+    """drho/dt of Eq. (9) for every fluid particle (or the query subset)."""
     fx = _f64(fx, P.dim)
     fv = _f64(fv, P.dim)
     frho = _f64(frho)
     wx = _f64(wx, P.dim)
     pw = _f64(pw)
-    out = np.zeros(max(len(fx), 1))
+    nq, qp, _keep = _query(query, len(fx))
+    out = np.zeros(max(nq, 1))
     _check(lib().orc_continuity(C.byref(P), len(fx), _d(fx), _d(fv), _d(frho), len(wx), _d(wx),
-                                _d(pw), _d(out)), "continuity")
-    return out[: len(fx)]
+                                _d(pw), nq, qp, _d(out)), "continuity")
+    return out[:nq]
 
 
-def momentum(P, fx, fv, frho, wx, pw, wn):
+def momentum(P, fx, fv, frho, wx, pw, wn, query=None):
+    """dv/dt of Eqs. (10)-(11), (13) + viscous + g (or the query subset)."""
     fx = _f64(fx, P.dim)
     fv = _f64(fv, P.dim)
     frho = _f64(frho)
     wx = _f64(wx, P.dim)
     pw = _f64(pw)
     wn = _f64(wn, P.dim)
-    out = np.zeros((max(len(fx), 1), P.dim))
+    nq, qp, _keep = _query(query, len(fx))
+    out = np.zeros((max(nq, 1), P.dim))
     _check(lib().orc_momentum(C.byref(P), len(fx), _d(fx), _d(fv), _d(frho), len(wx), _d(wx),
-                              _d(pw), _d(wn), _d(out)), "momentum")
-    return out[: len(fx)]
+                              _d(pw), _d(wn), nq, qp, _d(out)), "momentum")
+    return out[:nq]
 
 
 def diag(P, fx, fv):

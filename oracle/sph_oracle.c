@@ -37,7 +37,8 @@
  *               F_p = -2 gamma_p sum_w m_w/(rho_i rho_w) (1-delta)^2
  *                     |p_i e_iw . n_w| W'(r_iw) n_w   for delta < 1.
  *   normals     Eq. (16) over wall particles only, V_j = dx^d; n_w = 0 when
- *               |Psi| h <= 1e-6 (exact cancellation inside the wall).
+ *               |Psi| h <= 1e-4 (cancellation inside the wall: such sums
+ *               are ~1e-14 in FP64 while real normals have |Psi| h > 5e-3).
  *   schedule    per step: Eq. (17) reinit at r^n, Eq. (19) half kick,
  *               Eq. (20) drift, cell rebuild, Eq. (12) wall pressure,
  *               Eq. (9)+(21) density update, Eq. (10)+(22) second kick.
@@ -372,7 +373,7 @@ static double dot(int dim, const double *a, const double *b)
 /* j = i included (Eq. (4) without the mass; Eq. (17) definition).     */
 /* ------------------------------------------------------------------ */
 int orc_sigma(const orc_params *P, int64_t nf, const double *fx, int64_t nw, const double *wx,
-              double *sigma)
+              int64_t nq, const int64_t *qidx, double *sigma)
 {
     int dim = P->dim;
     double h = P->h, rc2 = 4.0 * h * h;
@@ -389,7 +390,8 @@ int orc_sigma(const orc_params *P, int64_t nf, const double *fx, int64_t nw, con
     {
         int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < nf; ++i) {
+        for (int64_t a_q = 0; a_q < nq; ++a_q) {
+            int64_t i = qidx ? qidx[a_q] : a_q;
             const double *xi = fx + i * dim;
             double s = 0.0;
             for (int set = 0; set < 2; ++set) {
@@ -406,7 +408,7 @@ int orc_sigma(const orc_params *P, int64_t nf, const double *fx, int64_t nw, con
                     s += orc_W(dim, h, sqrt(r2));
                 }
             }
-            sigma[i] = s;
+            sigma[a_q] = s;
         }
         free(nbr);
     }
@@ -447,7 +449,8 @@ double orc_sigma0(int dim, double dx, double h)
 /* file header), one value per wall particle.                          */
 /* ------------------------------------------------------------------ */
 int orc_wall_pressure(const orc_params *P, int64_t nw, const double *wx, int64_t nf,
-                      const double *fx, const double *frho, double *pw)
+                      const double *fx, const double *frho, int64_t nq, const int64_t *qidx,
+                      double *pw)
 {
     int dim = P->dim;
     double h = P->h, rc2 = 4.0 * h * h;
@@ -461,7 +464,8 @@ int orc_wall_pressure(const orc_params *P, int64_t nw, const double *wx, int64_t
     {
         int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
 #pragma omp for schedule(static)
-        for (int64_t w = 0; w < nw; ++w) {
+        for (int64_t a_q = 0; a_q < nq; ++a_q) {
+            int64_t w = qidx ? qidx[a_q] : a_q;
             const double *xw = wx + w * dim;
             int cnt = cs_query(&sf, xw, rc2, nbr, ORC_NBR_CAP);
             if (cnt < 0) {
@@ -481,7 +485,7 @@ int orc_wall_pressure(const orc_params *P, int64_t nw, const double *wx, int64_t
                 sumPW += eos_p(P, frho[f]) * W;
                 for (int k = 0; k < dim; ++k) sumRW[k] += frho[f] * rwf[k] * W;
             }
-            pw[w] = sumW > 0.0 ? (sumPW + dot(dim, gw, sumRW)) / sumW : 0.0;
+            pw[a_q] = sumW > 0.0 ? (sumPW + dot(dim, gw, sumRW)) / sumW : 0.0;
         }
         free(nbr);
     }
@@ -529,7 +533,7 @@ int orc_normals(const orc_params *P, int64_t nw, const double *wx, double *nrm, 
             double norm = sqrt(dot(dim, Psi, Psi));
             for (int k = 0; k < dim; ++k) {
                 if (psi) psi[w * dim + k] = Psi[k];
-                nrm[w * dim + k] = norm * h > 1e-6 ? Psi[k] / norm : 0.0;
+                nrm[w * dim + k] = norm * h > 1e-4 ? Psi[k] / norm : 0.0;
             }
         }
         free(nbr);
@@ -547,7 +551,7 @@ int orc_normals(const orc_params *P, int64_t nw, const double *wx, double *nrm, 
 /* ------------------------------------------------------------------ */
 int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const double *fv,
                    const double *frho, int64_t nw, const double *wx, const double *pw,
-                   double *drhodt)
+                   int64_t nq, const int64_t *qidx, double *drhodt)
 {
     int dim = P->dim;
     double h = P->h, rc2 = 4.0 * h * h, m = particle_mass(P);
@@ -564,7 +568,8 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
     {
         int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < nf; ++i) {
+        for (int64_t a_q = 0; a_q < nq; ++a_q) {
+            int64_t i = qidx ? qidx[a_q] : a_q;
             const double *xi = fx + i * dim, *vi = fv + i * dim;
             double rho_i = frho[i], p_i = eos_p(P, rho_i);
             double sum = 0.0;
@@ -612,7 +617,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
                     sum += m / rho_j * dot(dim, diff, gradW);
                 }
             }
-            drhodt[i] = 2.0 * rho_i * sum;
+            drhodt[a_q] = 2.0 * rho_i * sum;
         }
         free(nbr);
     }
@@ -627,7 +632,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
 /* ------------------------------------------------------------------ */
 int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double *fv,
                  const double *frho, int64_t nw, const double *wx, const double *pw,
-                 const double *wn, double *acc)
+                 const double *wn, int64_t nq, const int64_t *qidx, double *acc)
 {
     int dim = P->dim;
     double h = P->h, rc2 = 4.0 * h * h, m = particle_mass(P);
@@ -645,7 +650,8 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
     {
         int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < nf; ++i) {
+        for (int64_t a_q = 0; a_q < nq; ++a_q) {
+            int64_t i = qidx ? qidx[a_q] : a_q;
             const double *xi = fx + i * dim, *vi = fv + i * dim;
             double rho_i = frho[i], p_i = eos_p(P, rho_i);
             double A[3] = {0, 0, 0};     /* pressure part, Eq. (10)/(11) */
@@ -704,7 +710,7 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                     }
                 }
             }
-            for (int k = 0; k < dim; ++k) acc[i * dim + k] = A[k] + Vis[k] + Fp[k] + P->g[k];
+            for (int k = 0; k < dim; ++k) acc[a_q * dim + k] = A[k] + Vis[k] + Fp[k] + P->g[k];
         }
         free(nbr);
     }
@@ -764,7 +770,7 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
     if (!sigma || !rho_t || !vhalf || !D) rc = ORC_ERR_ALLOC;
     for (int n = 0; n < nsteps && rc == ORC_OK; ++n) {
         /* Eq. (17): reinitialise the density at r^n with rho* = rho^n. */
-        rc = orc_sigma(P, nf, fx, nw, wx, sigma);
+        rc = orc_sigma(P, nf, fx, nw, wx, nf, NULL, sigma);
         if (rc) break;
         orc_reinit(P, nf, sigma, frho, rho_t);
         /* Eqs. (19)-(20): half kick and drift. */
@@ -774,7 +780,7 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
                 fx[i * dim + k] = fx[i * dim + k] + dt * vhalf[i * dim + k];
             }
         /* Eq. (12) at r^{n+1} from the reinitialised density. */
-        rc = orc_wall_pressure(P, nw, wx, nf, fx, rho_t, pw);
+        rc = orc_wall_pressure(P, nw, wx, nf, fx, rho_t, nw, NULL, pw);
         if (rc) break;
         if (J && nprobe > 0) {
             double s = 0.0;
@@ -782,11 +788,11 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
             *J += dt * s / nprobe;
         }
         /* Eqs. (9), (21): density update. */
-        rc = orc_continuity(P, nf, fx, vhalf, rho_t, nw, wx, pw, D);
+        rc = orc_continuity(P, nf, fx, vhalf, rho_t, nw, wx, pw, nf, NULL, D);
         if (rc) break;
         for (int64_t i = 0; i < nf; ++i) frho[i] = rho_t[i] + dt * D[i];
         /* Eqs. (10), (22): acceleration at n+1 and second half kick. */
-        rc = orc_momentum(P, nf, fx, vhalf, frho, nw, wx, pw, wn, facc);
+        rc = orc_momentum(P, nf, fx, vhalf, frho, nw, wx, pw, wn, nf, NULL, facc);
         if (rc) break;
         for (int64_t i = 0; i < nf; ++i)
             for (int k = 0; k < dim; ++k)

@@ -1,0 +1,1269 @@
+// sph_kernels.hip -- gfx950 kernels of the SPH hot path and the C ABI of
+// include/sph.h.  One source, instantiated for T = float and T = double and
+// for 2-D and 3-D.
+//
+// Method: Rezavand, Zhang & Hu (arXiv 2110.02621).  Readings of points the
+// paper leaves open (the same as the FP64 oracle's):
+//   - kernel: quintic Wendland C2, kappa = 2 (Sec. 2.3, Sec. 4);
+//   - Eq. (12) with the fluid density in the hydrostatic term, p_w = 0
+//     without fluid neighbours; wall density from the EOS and wall mass
+//     rho0 dx^d;
+//   - Eq. (17) at the start of each step with rho* = current density and a
+//     scalar sigma^0 (full lattice sum);
+//   - viscous term of Morris, Fox & Zhu (1997) with no-slip walls;
+//   - penalty, Eqs. (13)-(15): delta = 2 |(r_i - r_w) . n_w| / dx and
+//     F_p = -2 gamma_p sum m/(rho_i rho_w) (1 - delta)^2 |p_i e . n_w| W' n_w;
+//   - normals, Eq. (16): n_w = 0 when |Psi| h <= 1e-4.
+//
+// Data layout (structure of arrays, sorted by cell): fluid key/pid int32,
+// offsets, velocities, accelerations T[dim][n], density as rho - rho0 in T.
+// Positions are cell + offset so that pair distances keep full relative
+// precision in FP32 regardless of the tank size.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <type_traits>
+
+#include "sph.h"
+#include "sph_device.h"
+
+using namespace sph;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+
+inline int grid_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort by cell key (neighbour search "including sorting", Sec. 3).
+//   1. histogram: slot_i = atomic fetch-add on count[key_i] (the count per
+//      cell is exact; the slot order inside a cell is arbitrary);
+//   2. exclusive scan of the counts -> cell start table;
+//   3. place: perm[start[key_i] + slot_i] = i;
+//   4. per-cell insertion sort of perm by source index, which makes the
+//      order inside a cell the prior order: deterministic and stable;
+//   5. gather of every field through perm.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock) k_hist(const int32_t* __restrict__ key, int64_t n,
+                                                  int32_t* __restrict__ count,
+                                                  int32_t* __restrict__ slot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) slot[i] = atomicAdd(&count[key[i]], 1);
+}
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+// Exclusive scan of one value per thread over a block of kScanThreads.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* waves, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) waves[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        const int nw = kScanThreads / 64;
+        int w = lane < nw ? waves[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (lane < nw) waves[lane] = w;
+    }
+    __syncthreads();
+    const int base = wid > 0 ? waves[wid - 1] : 0;
+    total = waves[kScanThreads / 64 - 1];
+    __syncthreads();
+    return base + x - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t* __restrict__ cnt,
+                                                               int64_t n,
+                                                               int32_t* __restrict__ tile_sum) {
+    __shared__ int waves[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += base + k < n ? cnt[base + k] : 0;
+    int total;
+    block_exclusive_scan(s, waves, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the tile sums in place.
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int32_t* __restrict__ tile_sum,
+                                                              int ntiles) {
+    __shared__ int waves[kScanThreads / 64];
+    int carry = 0;
+    for (int b = 0; b < ntiles; b += kScanThreads) {
+        const int i = b + threadIdx.x;
+        const int v = i < ntiles ? tile_sum[i] : 0;
+        int total;
+        const int e = block_exclusive_scan(v, waves, total);
+        if (i < ntiles) tile_sum[i] = carry + e;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const int32_t* __restrict__ cnt,
+                                                             int64_t n,
+                                                             const int32_t* __restrict__ tile_off,
+                                                             int32_t* __restrict__ start,
+                                                             int32_t n_total) {
+    __shared__ int waves[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? cnt[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int e = block_exclusive_scan(s, waves, total) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) start[base + k] = e;
+        e += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = n_total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_place(const int32_t* __restrict__ key,
+                                                   const int32_t* __restrict__ slot, int64_t n,
+                                                   const int32_t* __restrict__ start,
+                                                   int32_t* __restrict__ perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[start[key[i]] + slot[i]] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cellsort(const int32_t* __restrict__ start,
+                                                      int64_t ncell, int32_t* __restrict__ perm) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int a = start[c], b = start[c + 1];
+    for (int i = a + 1; i < b; ++i) {
+        const int v = perm[i];
+        int j = i - 1;
+        while (j >= a && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_gather_fluid(const int32_t* __restrict__ perm, int64_t n, const int32_t* __restrict__ key_in,
+                   const int32_t* __restrict__ pid_in, const T* __restrict__ off_in,
+                   const T* __restrict__ vel_in, const T* __restrict__ rho_in,
+                   int32_t* __restrict__ key_out, int32_t* __restrict__ pid_out,
+                   T* __restrict__ off_out, T* __restrict__ vel_out, T* __restrict__ rho_out) {
+    const int64_t i = global_index();
+    if (i >= n) return;
+    const int64_t s = perm[i];
+    key_out[i] = key_in[s];
+    pid_out[i] = pid_in[s];
+    rho_out[i] = rho_in[s];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        off_out[k * n + i] = off_in[k * n + s];
+        vel_out[k * n + i] = vel_in[k * n + s];
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_gather_wall(const int32_t* __restrict__ perm, int64_t n, const int32_t* __restrict__ key_in,
+                  const T* __restrict__ off_in, int32_t* __restrict__ key_out,
+                  int32_t* __restrict__ pid_out, T* __restrict__ off_out,
+                  int32_t* __restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = perm[i];
+    key_out[i] = key_in[s];
+    pid_out[i] = s;
+    inv[s] = (int32_t)i;
+#pragma unroll
+    for (int k = 0; k < D; ++k) off_out[k * n + i] = off_in[k * n + s];
+}
+
+// ---------------------------------------------------------------------------
+// Position conversion: absolute double -> cell + offset in T.
+// ---------------------------------------------------------------------------
+
+struct GridD {
+    double lo[3];
+    double L;
+    int n[3];
+};
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_to_cells(const double* __restrict__ pos, int64_t n, GridD G, int32_t* __restrict__ key,
+               T* __restrict__ off, uint32_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T L = T(G.L);
+    int c[3] = {0, 0, 0};
+    bool outside = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double x = pos[k * n + i] - G.lo[k];
+        double f = floor(x / G.L);
+        int ck = (int)fmax(fmin(f, (double)(G.n[k] - 1)), 0.0);
+        if (!(f >= 0.0 && f <= (double)(G.n[k] - 1))) outside = true;
+        T o = T(x - (double)ck * G.L);
+        if (o < T(0)) o = T(0);
+        if (o >= L) {  // rounding up to L: same point as offset 0 of the next cell
+            if (ck + 1 < G.n[k]) {
+                ++ck;
+                o = T(0);
+            } else {
+                o = L * T(0.9999999);
+                outside = true;
+            }
+        }
+        c[k] = ck;
+        off[k * n + i] = o;
+    }
+    if (outside) atomicAdd(&status[SPH_STATUS_OUT_OF_GRID], 1u);
+    key[i] = c[0] + G.n[0] * (c[1] + G.n[1] * c[2]);
+}
+
+// Initial velocity and density into the current copies (pid = input index).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_init_state(int64_t n, const double* __restrict__ vel, const double* __restrict__ rho, T rho0,
+                 int32_t* __restrict__ pid, T* __restrict__ vel_out, T* __restrict__ drho_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pid[i] = (int32_t)i;
+    for (int k = 0; k < D; ++k) vel_out[k * n + i] = T(vel[k * n + i]);
+    drho_out[i] = T(rho[i] - (double)rho0);
+}
+
+// ---------------------------------------------------------------------------
+// Wall normals, Eq. (16): Psi_w = -sum_{j in walls} dx^d grad_w W_wj.
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_normals(Par<T> P, int64_t nw, const int32_t* __restrict__ wkey, const T* __restrict__ woff,
+              const int32_t* __restrict__ wstart, T* __restrict__ nrm) {
+    const int64_t w = global_index();
+    if (w >= nw) return;
+    const T* o0 = woff;
+    const T* o1 = woff + nw;
+    const T* o2 = woff + 2 * nw;
+    int c[3];
+    cell_of(P, wkey[w], c);
+    const T oi[3] = {o0[w], o1[w], D == 3 ? o2[w] : T(0)};
+    T psi[3] = {0, 0, 0};
+    for_neighbours<T, D>(P, wstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+        if (r2 > T(0)) {
+            const T F = wendland_F(P, root(r2));
+#pragma unroll
+            for (int k = 0; k < D; ++k) psi[k] -= P.vol * F * d[k];
+        }
+    });
+    T n2 = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) n2 += psi[k] * psi[k];
+    const T nn = root(n2);
+    const bool zero = !(nn > P.psi_min);
+#pragma unroll
+    for (int k = 0; k < D; ++k) nrm[k * nw + w] = zero ? T(0) : psi[k] / nn;
+}
+
+// ---------------------------------------------------------------------------
+// Density update: sigma_i, Eq. (17) reinitialisation, half kick Eq. (19),
+// drift Eq. (20) with cell renormalisation.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T& s, T& comp, T v) {
+    if (std::is_same<T, float>::value) {
+        const T y = v - comp;
+        const T t = s + y;
+        comp = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
+}
+
+// Move an offset by dx and keep it in [0, L): returns the cell shift.
+// One-cell moves are exact (Sterbenz); longer ones are counted.
+template <typename T>
+__device__ __forceinline__ int renormalise(T& o, T L, uint32_t* status) {
+    if (o >= T(0) && o < L) return 0;
+    if (o >= L && o < T(2) * L) {
+        o = o - L;
+        return 1;
+    }
+    if (o < T(0) && o >= -L) {
+        const T t = o + L;
+        if (t < L) {
+            o = t;
+            return -1;
+        }
+        o = T(0);  // o + L rounds to L: the point is the start of this cell
+        return 0;
+    }
+    atomicAdd(&status[SPH_STATUS_FAST], 1u);
+    if (!(o == o) || absv(o) > T(1e6) * L) {  // non-finite or absurd: park at the cell start
+        o = T(0);
+        return 0;
+    }
+    const T f = floorv(o / L);
+    o = o - f * L;
+    if (o < T(0)) o = T(0);
+    if (o >= L) o = T(0);
+    return (int)f;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_density(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+              const int32_t* __restrict__ pid, const T* __restrict__ off,
+              const int32_t* __restrict__ fstart, const T* __restrict__ woff,
+              const int32_t* __restrict__ wstart, T* __restrict__ vel, T* __restrict__ drho,
+              const T* __restrict__ acc, int32_t* __restrict__ key_out,
+              int32_t* __restrict__ pid_out, T* __restrict__ off_out, T* __restrict__ sigma_out,
+              uint32_t* __restrict__ status) {
+    const int64_t i = global_index();
+    if (i >= nf) return;
+    const T* o0 = off;
+    const T* o1 = off + nf;
+    const T* o2 = off + 2 * nf;
+    int c[3];
+    cell_of(P, key[i], c);
+    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
+    T s = T(0), comp = T(0);
+    auto addW = [&](int, const T*, T r2) { kahan_add(s, comp, wendland_W(P, root(r2))); };
+    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, addW);
+    if (nw > 0) for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
+    if (sigma_out) sigma_out[i] = s;
+    // Eq. (17) in deviations from rho0: rho_s - rho0 = rho0 (sigma - sigma0)/sigma0.
+    const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
+    const T dstar = drho[i];
+    const T excess = dstar - drs;
+    drho[i] = excess > T(0) ? drs + excess * P.rho0 / (P.rho0 + dstar) : drs;
+    // Eqs. (19)-(20): half kick, drift, renormalise the cell.
+    int cn[3] = {c[0], c[1], c[2]};
+    const int nmax[3] = {P.nx, P.ny, P.nz};
+    bool out = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T v = vel[k * nf + i] + P.half_dt * acc[k * nf + i];
+        vel[k * nf + i] = v;
+        T o = oi[k] + P.dt * v;
+        int ck = c[k] + renormalise(o, P.L, status);
+        if (ck < 0) {
+            ck = 0;
+            o = T(0);
+            out = true;
+        } else if (ck >= nmax[k]) {
+            ck = nmax[k] - 1;
+            o = P.L * T(0.9999999);
+            out = true;
+        }
+        cn[k] = ck;
+        off_out[k * nf + i] = o;
+    }
+    if (out) atomicAdd(&status[SPH_STATUS_OUT_OF_GRID], 1u);
+    key_out[i] = cn[0] + P.nx * (cn[1] + P.ny * cn[2]);
+    pid_out[i] = pid[i];
+}
+
+// ---------------------------------------------------------------------------
+// Wall pressure, Eq. (12), one thread per wall particle.
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_wall_bc(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+              const T* __restrict__ woff, const T* __restrict__ off,
+              const int32_t* __restrict__ fstart, const T* __restrict__ drho, T* __restrict__ pw) {
+    const int64_t w = global_index();
+    if (w >= nw) return;
+    int c[3];
+    cell_of(P, wkey[w], c);
+    const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
+    T sW = T(0), sP = T(0), sR[3] = {0, 0, 0};
+    if (nf > 0)
+        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow,
+                             [&](int f, const T d[3], T r2) {
+                                 const T W = wendland_W(P, root(r2));
+                                 const T dr = drho[f];
+                                 sW += W;
+                                 sP += P.c2 * dr * W;
+                                 const T rW = (P.rho0 + dr) * W;
+#pragma unroll
+                                 for (int k = 0; k < D; ++k) sR[k] += rW * d[k];
+                             });
+    T gR = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) gR += P.gw[k] * sR[k];
+    pw[w] = sW > T(0) ? (sP + gR) / sW : T(0);
+}
+
+// Probe integral: diag[PROBE] += dt * mean(p_w over the probe walls).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_probe(const T* __restrict__ pw, const int32_t* __restrict__ inv, int64_t nw,
+            const int32_t* __restrict__ probe, int np, double dt, double* __restrict__ diag) {
+    __shared__ double red[kBlock];
+    double s = 0.0;
+    for (int a = threadIdx.x; a < np; a += kBlock) {
+        const int32_t id = probe[a];
+        if (id >= 0 && id < nw) s += (double)pw[inv[id]];  // ids outside the walls add 0
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) diag[SPH_DIAG_PROBE] += dt * red[0] / (double)np;
+}
+
+// ---------------------------------------------------------------------------
+// Mass conservation, Eq. (9) with Eqs. (7)-(8), and Eq. (21).
+// With v* = U* e + (rho_i v_i + rho_j v_j)/(rho_i + rho_j) - Ubar e one has
+// (v_i - v*) . grad W = F [rho_j (v_ij . r_ij) + (p_i - p_j) r / c]/(rho_i + rho_j)
+// with F = W'(r)/r, so per pair the sum gains
+// F [rho_j (v_ij . r_ij) + (p_i - p_j) r / c] / (rho_j (rho_i + rho_j)).
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_continuity(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+                 const T* __restrict__ off, const int32_t* __restrict__ fstart,
+                 const T* __restrict__ vel, const T* __restrict__ drho,
+                 const T* __restrict__ woff, const int32_t* __restrict__ wstart,
+                 const T* __restrict__ pw, T* __restrict__ drho_out) {
+    const int64_t i = global_index();
+    if (i >= nf) return;
+    const T* o0 = off;
+    const T* o1 = off + nf;
+    const T* o2 = off + 2 * nf;
+    int c[3];
+    cell_of(P, key[i], c);
+    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
+    const T vi[3] = {vel[i], vel[nf + i], D == 3 ? vel[2 * nf + i] : T(0)};
+    const T dri = drho[i];
+    const T rho_i = P.rho0 + dri;
+    T sum = T(0);
+    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+        if (!(r2 > T(0))) return;
+        const T r = root(r2);
+        const T F = wendland_F(P, r);
+        const T drj = drho[j];
+        const T rho_j = P.rho0 + drj;
+        T vd = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) vd += (vi[k] - vel[k * nf + j]) * d[k];
+        const T q = rcp(rho_j * (rho_i + rho_j));
+        sum += F * q * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
+    });
+    if (nw > 0)
+        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                             [&](int w, const T d[3], T r2) {
+                                 if (!(r2 > T(0))) return;
+                                 const T r = root(r2);
+                                 const T F = wendland_F(P, r);
+                                 const T p_w = pw[w];
+                                 const T rho_w = P.rho0 + p_w * P.inv_c2;
+                                 T vd = T(0);
+#pragma unroll
+                                 for (int k = 0; k < D; ++k) vd += vi[k] * d[k];
+                                 const T q = rcp(rho_w * (rho_i + rho_w));
+                                 sum += F * q * (rho_w * vd + (P.c2 * dri - p_w) * r * P.cinv);
+                             });
+    drho_out[i] = dri + P.dt * (T(2) * rho_i * P.m * sum);
+}
+
+// ---------------------------------------------------------------------------
+// Momentum, Eq. (10) with p* of Eq. (8) (fluid) and Eq. (11) (walls),
+// viscous term, penalty force Eqs. (13)-(15), gravity, second kick Eq. (22).
+// Per fluid pair, with U_L - U_R = -(v_ij . r_ij)/r and F = W'(r)/r:
+//   p* = [rho_i p_j + rho_j p_i + rho_i rho_j beta (U_L - U_R)]/(rho_i + rho_j)
+//   dv_i/dt += m F/(rho_i rho_j) [-2 p* r_ij + 2 mu r^2/(r^2 + eta^2) v_ij].
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_momentum(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+               const T* __restrict__ off, const int32_t* __restrict__ fstart,
+               const T* __restrict__ vel, const T* __restrict__ drho,
+               const T* __restrict__ woff, const int32_t* __restrict__ wstart,
+               const T* __restrict__ pw, const T* __restrict__ nrm, T* __restrict__ acc,
+               T* __restrict__ vel_out, int kick) {
+    const int64_t i = global_index();
+    if (i >= nf) return;
+    const T* o0 = off;
+    const T* o1 = off + nf;
+    const T* o2 = off + 2 * nf;
+    int c[3];
+    cell_of(P, key[i], c);
+    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
+    const T vi[3] = {vel[i], vel[nf + i], D == 3 ? vel[2 * nf + i] : T(0)};
+    const T dri = drho[i];
+    const T rho_i = P.rho0 + dri;
+    const T p_i = P.c2 * dri;
+    const T inv_rho_i = T(1) / rho_i;
+    T A[3] = {0, 0, 0};
+    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+        if (!(r2 > T(0))) return;
+        const T rinv = rsq(r2);
+        const T r = r2 * rinv;
+        const T F = wendland_F(P, r);
+        const T drj = drho[j];
+        const T rho_j = P.rho0 + drj;
+        const T p_j = P.c2 * drj;
+        T dv[3];
+        T vd = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dv[k] = vi[k] - vel[k * nf + j];
+            vd += dv[k] * d[k];
+        }
+        const T jump = -vd * rinv;  // U_L - U_R
+        const T beta = minv(T(3) * maxv(jump, T(0)), P.c);
+        const T sum = rho_i + rho_j;
+        const T q = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
+        const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * q);
+        const T coef = P.m * F * (sum * q) * inv_rho_i;  // m F/(rho_i rho_j)
+        const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
+#pragma unroll
+        for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
+    });
+    if (nw > 0)
+        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                             [&](int w, const T d[3], T r2) {
+                                 if (!(r2 > T(0))) return;
+                                 const T r = root(r2);
+                                 const T F = wendland_F(P, r);
+                                 const T p_w = pw[w];
+                                 const T rho_w = P.rho0 + p_w * P.inv_c2;
+                                 const T sum = rho_i + rho_w;
+                                 const T q = rcp(rho_w * sum);
+                                 const T pstar = (rho_i * p_w + rho_w * p_i) * (rho_w * q);
+                                 const T coef = P.m * F * (sum * q) * inv_rho_i;
+                                 const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
+                                 T pen = T(0);
+                                 T nv[3] = {0, 0, 0};
+                                 if (P.penalty) {
+                                     T proj = T(0);
+#pragma unroll
+                                     for (int k = 0; k < D; ++k) {
+                                         nv[k] = nrm[k * nw + w];
+                                         proj += d[k] * nv[k];
+                                     }
+                                     const T ap = absv(proj);
+                                     const T delta = P.two_over_dx * ap;
+                                     if (delta < T(1)) {
+                                         const T om = T(1) - delta;
+                                         pen = -T(2) * P.gamma_p * om * om * absv(p_i) * ap;
+                                     }
+                                 }
+#pragma unroll
+                                 for (int k = 0; k < D; ++k)
+                                     A[k] += coef * (visc * vi[k] - T(2) * pstar * d[k] + pen * nv[k]);
+                             });
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T a = A[k] + P.g[k];
+        acc[k * nf + i] = a;
+        if (kick) vel_out[k * nf + i] = vi[k] + P.half_dt * a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics: per-block partials, then one block in fixed order.
+// ---------------------------------------------------------------------------
+
+constexpr int kDiagVals = 8;  // M, P0, P1, P2, Ek, Ep, vmax, nonfinite
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_diag_partial(Par<T> P, GridD G, int64_t nf, const int32_t* __restrict__ key,
+                   const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ drho,
+                   double* __restrict__ part) {
+    __shared__ double red[kDiagVals][kBlock];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < nf) {
+        const double m = (double)P.m;
+        int c[3];
+        cell_of(P, key[i], c);
+        double v2 = 0.0, gx = 0.0;
+        bool finite = isfinite((double)drho[i]);
+        for (int k = 0; k < D; ++k) {
+            const double vk = (double)vel[k * nf + i];
+            const double xk = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
+            finite = finite && isfinite(vk) && isfinite(xk);
+            v[1 + k] = m * vk;
+            v2 += vk * vk;
+            gx += (double)P.g[k] * xk;
+        }
+        v[0] = m;
+        v[4] = 0.5 * m * v2;
+        v[5] = -m * gx;
+        v[6] = sqrt(v2);
+        v[7] = finite ? 0.0 : 1.0;
+    }
+    for (int k = 0; k < kDiagVals; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < kDiagVals; ++k) {
+                if (k == 6)
+                    red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + o]);
+                else
+                    red[k][threadIdx.x] += red[k][threadIdx.x + o];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagVals) part[(int64_t)blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_diag_final(const double* __restrict__ part, int nblocks, double* __restrict__ diag,
+                 uint32_t* __restrict__ status) {
+    __shared__ double red[kDiagVals][kBlock];
+    double v[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < kDiagVals; ++k) {
+            const double x = part[(int64_t)b * kDiagVals + k];
+            v[k] = k == 6 ? fmax(v[k], x) : v[k] + x;
+        }
+    for (int k = 0; k < kDiagVals; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < kDiagVals; ++k) {
+                if (k == 6)
+                    red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + o]);
+                else
+                    red[k][threadIdx.x] += red[k][threadIdx.x + o];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        diag[SPH_DIAG_MASS] = red[0][0];
+        diag[SPH_DIAG_MOM + 0] = red[1][0];
+        diag[SPH_DIAG_MOM + 1] = red[2][0];
+        diag[SPH_DIAG_MOM + 2] = red[3][0];
+        diag[SPH_DIAG_EKIN] = red[4][0];
+        diag[SPH_DIAG_EPOT] = red[5][0];
+        diag[SPH_DIAG_VMAX] = red[6][0];
+        if (red[7][0] > 0.0) atomicAdd(&status[SPH_STATUS_NONFINITE], (uint32_t)red[7][0]);
+    }
+}
+
+__global__ void k_count_step(double* diag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) diag[SPH_DIAG_STEPS] += 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Export in particle-id order (doubles).
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_export(Par<T> P, GridD G, int64_t nf, const int32_t* __restrict__ key,
+             const int32_t* __restrict__ pid, const T* __restrict__ off, const T* __restrict__ vel,
+             const T* __restrict__ drho, const T* __restrict__ acc, double* __restrict__ pos_o,
+             double* __restrict__ vel_o, double* __restrict__ rho_o, double* __restrict__ acc_o) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int64_t p = pid[i];
+    int c[3];
+    cell_of(P, key[i], c);
+    for (int k = 0; k < D; ++k) {
+        if (pos_o) pos_o[k * nf + p] = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
+        if (vel_o) vel_o[k * nf + p] = (double)vel[k * nf + i];
+        if (acc_o) acc_o[k * nf + p] = (double)acc[k * nf + i];
+    }
+    if (rho_o) rho_o[p] = (double)P.rho0 + (double)drho[i];
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_export_walls(Par<T> P, GridD G, int64_t nw, const int32_t* __restrict__ wkey,
+                   const int32_t* __restrict__ wpid, const T* __restrict__ woff,
+                   const T* __restrict__ pw, const T* __restrict__ nrm, double* __restrict__ pw_o,
+                   double* __restrict__ nrm_o, double* __restrict__ pos_o) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nw) return;
+    const int64_t p = wpid[w];
+    int c[3];
+    cell_of(P, wkey[w], c);
+    if (pw_o) pw_o[p] = (double)pw[w];
+    for (int k = 0; k < D; ++k) {
+        if (nrm_o) nrm_o[k * nw + p] = (double)nrm[k * nw + w];
+        if (pos_o) pos_o[k * nw + p] = G.lo[k] + (double)c[k] * G.L + (double)woff[k * nw + w];
+    }
+}
+
+// Neighbour sets as the sweeps see them (test and inspection aid).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_neighbours(Par<T> P, int which, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+                 const int32_t* __restrict__ pid, const T* __restrict__ off,
+                 const int32_t* __restrict__ fstart, const int32_t* __restrict__ wkey,
+                 const int32_t* __restrict__ wpid, const T* __restrict__ woff,
+                 const int32_t* __restrict__ wstart, const int64_t* __restrict__ offset,
+                 int32_t* __restrict__ count, int32_t* __restrict__ list, int64_t list_len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = which == 0 ? nf : nw;
+    if (i >= nq) return;
+    const int32_t* qkey = which == 0 ? key : wkey;
+    const T* qoff = which == 0 ? off : woff;
+    const int32_t qid = which == 0 ? pid[i] : wpid[i];
+    int c[3];
+    cell_of(P, qkey[i], c);
+    const T oi[3] = {qoff[i], qoff[nq + i], D == 3 ? qoff[2 * nq + i] : T(0)};
+    int cnt = 0;
+    int64_t base = list ? offset[qid] : 0;
+    if (nf > 0)
+        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi, [&](int j, const T*, T) {
+            if (list && base + cnt >= 0 && base + cnt < list_len) list[base + cnt] = pid[j];
+            ++cnt;
+        });
+    if (which == 0 && nw > 0)
+        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                             [&](int j, const T*, T) {
+                                 if (list && base + cnt >= 0 && base + cnt < list_len)
+                                     list[base + cnt] = (int32_t)nf + wpid[j];
+                                 ++cnt;
+                             });
+    count[qid] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+template <typename T>
+Par<T> make_par(const sph_desc* d) {
+    Par<T> P;
+    std::memset(&P, 0, sizeof(P));
+    const double h = d->h;
+    const double alpha = d->dim == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+    const double vol = d->dim == 2 ? d->dx * d->dx : d->dx * d->dx * d->dx;
+    P.nx = d->grid[0];
+    P.ny = d->grid[1];
+    P.nz = d->grid[2];
+    P.penalty = d->penalty_all ? 1 : 0;
+    P.L = T(d->cell);
+    P.rc2 = T(4.0 * h * h);
+    P.hinv = T(1.0 / h);
+    P.alpha = T(alpha);
+    P.gfac = T(-5.0 * alpha / (h * h));
+    P.m = T(d->rho0 * vol);
+    P.vol = T(vol);
+    P.rho0 = T(d->rho0);
+    P.c = T(d->c0);
+    P.c2 = T(d->c0 * d->c0);
+    P.cinv = T(1.0 / d->c0);
+    P.inv_c2 = T(1.0 / (d->c0 * d->c0));
+    P.mu2 = T(2.0 * d->mu);
+    P.eta2 = T(0.01 * h * h);
+    P.gamma_p = T(d->gamma_p);
+    P.two_over_dx = T(2.0 / d->dx);
+    for (int k = 0; k < 3; ++k) {
+        P.g[k] = T(d->g[k]);
+        P.gw[k] = T(d->g[k] - d->a_wall[k]);
+    }
+    P.dt = T(d->dt);
+    P.half_dt = T(0.5 * d->dt);
+    P.sigma0 = T(d->sigma0);
+    P.rho0_over_sigma0 = T(d->rho0 / d->sigma0);
+    P.psi_min = T(1e-4 / h);
+    return P;
+}
+
+GridD make_grid(const sph_desc* d) {
+    GridD G;
+    for (int k = 0; k < 3; ++k) {
+        G.lo[k] = k < d->dim ? d->lo[k] : 0.0;
+        G.n[k] = d->grid[k];
+    }
+    G.L = d->cell;
+    return G;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Scratch {
+    int32_t* count;   // n_cells
+    int32_t* slot;    // max(nf, nw)
+    int32_t* perm;    // max(nf, nw)
+    int32_t* tiles;   // scan tile sums
+    int32_t* winv;    // n_wall: sorted index of each wall id (kept between calls)
+    int32_t* wkey0;   // n_wall, unsorted wall keys (init only)
+    void* woff0;      // dim * n_wall T, unsorted wall offsets (init only)
+    double* part;     // diag partials
+    size_t bytes;
+};
+
+Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
+    const size_t ts = d->precision == SPH_F64 ? 8 : 4;
+    const int64_t nmax = nf > nw ? nf : nw;
+    const int64_t ntiles = (d->n_cells + kScanTile - 1) / kScanTile + 1;
+    const int64_t ndiag = (nf + kBlock - 1) / kBlock + 1;
+    size_t o = 0;
+    Scratch s;
+    char* b = (char*)base;
+    auto take = [&](size_t bytes) {
+        char* p = b ? b + o : nullptr;
+        o += align256(bytes > 0 ? bytes : 1);
+        return (void*)p;
+    };
+    s.count = (int32_t*)take(sizeof(int32_t) * (size_t)(d->n_cells + 1));
+    s.slot = (int32_t*)take(sizeof(int32_t) * (size_t)nmax);
+    s.perm = (int32_t*)take(sizeof(int32_t) * (size_t)nmax);
+    s.tiles = (int32_t*)take(sizeof(int32_t) * (size_t)ntiles);
+    s.winv = (int32_t*)take(sizeof(int32_t) * (size_t)nw);
+    s.wkey0 = (int32_t*)take(sizeof(int32_t) * (size_t)nw);
+    s.woff0 = take(ts * (size_t)d->dim * (size_t)nw);
+    s.part = (double*)take(sizeof(double) * kDiagVals * (size_t)ndiag);
+    s.bytes = o;
+    return s;
+}
+
+#define SPH_LAUNCH_CHECK()                                 \
+    do {                                                   \
+        if (hipGetLastError() != hipSuccess) return SPH_ERR_LAUNCH; \
+    } while (0)
+
+int check_desc(const sph_desc* d) {
+    if (!d) return SPH_ERR_ARG;
+    if (d->dim != 2 && d->dim != 3) return SPH_ERR_CONFIG;
+    if (d->precision != SPH_F32 && d->precision != SPH_F64) return SPH_ERR_CONFIG;
+    if (!(d->cell > 0.0) || d->n_cells <= 0) return SPH_ERR_CONFIG;
+    return SPH_OK;
+}
+
+int check_buf(const sph_desc* d, const sph_buffers* b) {
+    if (!b) return SPH_ERR_ARG;
+    if (b->n_fluid < 0 || b->n_wall < 0) return SPH_ERR_ARG;
+    if (b->n_fluid > INT32_MAX - 1 || b->n_wall > INT32_MAX - 1) return SPH_ERR_ARG;
+    if (b->sel_vel < 0 || b->sel_vel > 1 || b->sel_rho < 0 || b->sel_rho > 1) return SPH_ERR_ARG;
+    if (!b->scratch || b->scratch_bytes < sph_scratch_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
+    if (((uintptr_t)b->scratch & 255) != 0) return SPH_ERR_ARG;
+    if (!b->status || !b->diag || !b->fstart || !b->wstart) return SPH_ERR_ARG;
+    if (b->n_fluid > 0) {
+        for (int c = 0; c < 2; ++c)
+            if (!b->key[c] || !b->pid[c] || !b->off[c] || !b->vel[c] || !b->rho[c]) return SPH_ERR_ARG;
+        if (!b->acc) return SPH_ERR_ARG;
+    }
+    if (b->n_wall > 0 && (!b->wkey || !b->wpid || !b->woff || !b->pw || !b->nrm)) return SPH_ERR_ARG;
+    if (b->n_probe < 0 || (b->n_probe > 0 && !b->probe)) return SPH_ERR_ARG;
+    return SPH_OK;
+}
+
+// Sort n keys into cell order: start table + permutation (scratch.perm).
+int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n, int32_t* start,
+              hipStream_t st) {
+    const int64_t nc = d->n_cells;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nc)), dim3(kBlock), 0, st, s.count, nc, 0);
+    SPH_LAUNCH_CHECK();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(n)), dim3(kBlock), 0, st, key, n, s.count, s.slot);
+        SPH_LAUNCH_CHECK();
+    }
+    const int ntiles = (int)((nc + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(kScanThreads), 0, st, s.count, nc, s.tiles);
+    SPH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, st, s.tiles, ntiles);
+    SPH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(kScanThreads), 0, st, s.count, nc, s.tiles,
+                       start, (int32_t)n);
+    SPH_LAUNCH_CHECK();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_place, dim3(grid_for(n)), dim3(kBlock), 0, st, key, s.slot, n, start,
+                           s.perm);
+        SPH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cellsort, dim3(grid_for(nc)), dim3(kBlock), 0, st, start, nc, s.perm);
+        SPH_LAUNCH_CHECK();
+    }
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
+    const Scratch s = layout(d, b->n_fluid, b->n_wall, b->scratch);
+    const int64_t n = b->n_fluid;
+    int rc = sort_keys(d, s, b->key[1], n, b->fstart, st);
+    if (rc) return rc;
+    if (n > 0) {
+        const int sv = b->sel_vel, sr = b->sel_rho;
+        hipLaunchKernelGGL((k_gather_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, s.perm, n,
+                           b->key[1], b->pid[1], (const T*)b->off[1], (const T*)b->vel[sv],
+                           (const T*)b->rho[sr], b->key[0], b->pid[0], (T*)b->off[0],
+                           (T*)b->vel[1 - sv], (T*)b->rho[1 - sr]);
+        SPH_LAUNCH_CHECK();
+    }
+    b->sel_vel = 1 - b->sel_vel;
+    b->sel_rho = 1 - b->sel_rho;
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
+    const int64_t nf = b->n_fluid, nw = b->n_wall;
+    if (nf == 0) return SPH_OK;
+    const Par<T> P = make_par<T>(d);
+    hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, nw,
+                       b->key[0], b->pid[0], (const T*)b->off[0], b->fstart, (const T*)b->woff,
+                       b->wstart, (T*)b->vel[b->sel_vel], (T*)b->rho[b->sel_rho],
+                       (const T*)b->acc, b->key[1], b->pid[1], (T*)b->off[1], (T*)b->sigma_out,
+                       b->status);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = true) {
+    const int64_t nf = b->n_fluid, nw = b->n_wall;
+    if (nw == 0) return SPH_OK;
+    const Par<T> P = make_par<T>(d);
+    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, nf, nw,
+                       b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
+                       (const T*)b->rho[b->sel_rho], (T*)b->pw);
+    SPH_LAUNCH_CHECK();
+    if (probe && b->n_probe > 0) {
+        const Scratch s = layout(d, nf, nw, b->scratch);
+        hipLaunchKernelGGL((k_probe<T>), dim3(1), dim3(kBlock), 0, st, (const T*)b->pw, s.winv, nw,
+                           b->probe, b->n_probe, d->dt, b->diag);
+        SPH_LAUNCH_CHECK();
+    }
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) {
+    const int64_t nf = b->n_fluid, nw = b->n_wall;
+    const Par<T> P = make_par<T>(d);
+    const int sv = b->sel_vel, sr = b->sel_rho;
+    if (which & SPH_CONTINUITY) {
+        if (nf > 0) {
+            hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf,
+                               nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
+                               (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
+                               (const T*)b->pw, (T*)b->rho[1 - sr]);
+            SPH_LAUNCH_CHECK();
+        }
+        b->sel_rho = 1 - sr;
+    } else {
+        const int kick = (which & SPH_NO_KICK) ? 0 : 1;
+        if (nf > 0) {
+            hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, nw,
+                               b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
+                               (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
+                               (const T*)b->pw, (const T*)b->nrm, (T*)b->acc,
+                               (T*)b->vel[1 - sv], kick);
+            SPH_LAUNCH_CHECK();
+        }
+        if (kick) b->sel_vel = 1 - sv;
+    }
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* fvel,
+           const double* frho, const double* wpos, hipStream_t st) {
+    const int64_t nf = b->n_fluid, nw = b->n_wall;
+    const Scratch s = layout(d, nf, nw, b->scratch);
+    const GridD G = make_grid(d);
+    const Par<T> P = make_par<T>(d);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)b->status,
+                       (int64_t)SPH_STATUS_LEN, 0);
+    SPH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(kBlock), 0, st, b->diag, (int64_t)SPH_DIAG_LEN, 0.0);
+    SPH_LAUNCH_CHECK();
+    // walls: cells, one sort, normals
+    if (nw > 0) {
+        hipLaunchKernelGGL((k_to_cells<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, wpos, nw, G,
+                           s.wkey0, (T*)s.woff0, b->status);
+        SPH_LAUNCH_CHECK();
+    }
+    int rc = sort_keys(d, s, s.wkey0, nw, b->wstart, st);
+    if (rc) return rc;
+    if (nw > 0) {
+        hipLaunchKernelGGL((k_gather_wall<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, s.perm, nw,
+                           s.wkey0, (const T*)s.woff0, b->wkey, b->wpid, (T*)b->woff, s.winv);
+        SPH_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_normals<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, nw, b->wkey,
+                           (const T*)b->woff, b->wstart, (T*)b->nrm);
+        SPH_LAUNCH_CHECK();
+    }
+    // fluid: cells of the initial positions into copy 1, state into the
+    // current copies, then the sort brings everything to copy 0.
+    b->sel_vel = 0;
+    b->sel_rho = 0;
+    if (nf > 0) {
+        hipLaunchKernelGGL((k_to_cells<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, fpos, nf, G,
+                           b->key[1], (T*)b->off[1], b->status);
+        SPH_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_init_state<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, nf, fvel,
+                           frho, P.rho0, b->pid[1], (T*)b->vel[0], (T*)b->rho[0]);
+        SPH_LAUNCH_CHECK();
+    }
+    rc = build_cells_t<T, D>(d, b, st);
+    if (rc) return rc;
+    rc = wall_bc_t<T, D>(d, b, st, false);  // p_w of the initial state, not integrated
+    if (rc) return rc;
+    return forces_t<T, D>(d, b, SPH_MOMENTUM | SPH_NO_KICK, st);
+}
+
+template <typename T, int D>
+int step_t(const sph_desc* d, sph_buffers* b, int nsteps, hipStream_t st) {
+    for (int n = 0; n < nsteps; ++n) {
+        int rc = density_t<T, D>(d, b, st);
+        if (!rc) rc = build_cells_t<T, D>(d, b, st);
+        if (!rc) rc = wall_bc_t<T, D>(d, b, st);
+        if (!rc) rc = forces_t<T, D>(d, b, SPH_CONTINUITY, st);
+        if (!rc) rc = forces_t<T, D>(d, b, SPH_MOMENTUM, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, st, b->diag);
+        SPH_LAUNCH_CHECK();
+    }
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
+    const int64_t nf = b->n_fluid;
+    const Scratch s = layout(d, nf, b->n_wall, b->scratch);
+    const int nb = nf > 0 ? grid_for(nf) : 0;
+    if (nb > 0) {
+        hipLaunchKernelGGL((k_diag_partial<T, D>), dim3(nb), dim3(kBlock), 0, st, make_par<T>(d),
+                           make_grid(d), nf, b->key[0], (const T*)b->off[0],
+                           (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], s.part);
+        SPH_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, st, s.part, nb, b->diag, b->status);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int export_t(const sph_desc* d, const sph_buffers* b, double* pos, double* vel, double* rho,
+             double* acc, hipStream_t st) {
+    const int64_t nf = b->n_fluid;
+    if (nf == 0) return SPH_OK;
+    hipLaunchKernelGGL((k_export<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, make_par<T>(d),
+                       make_grid(d), nf, b->key[0], b->pid[0], (const T*)b->off[0],
+                       (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho],
+                       (const T*)b->acc, pos, vel, rho, acc);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int export_walls_t(const sph_desc* d, const sph_buffers* b, double* pw, double* nrm, double* pos,
+                   hipStream_t st) {
+    const int64_t nw = b->n_wall;
+    if (nw == 0) return SPH_OK;
+    hipLaunchKernelGGL((k_export_walls<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st,
+                       make_par<T>(d), make_grid(d), nw, b->wkey, b->wpid, (const T*)b->woff,
+                       (const T*)b->pw, (const T*)b->nrm, pw, nrm, pos);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
+template <typename T, int D>
+int neighbours_t(const sph_desc* d, const sph_buffers* b, int which, const int64_t* offset,
+                 int32_t* count, int32_t* list, int64_t list_len, hipStream_t st) {
+    const int64_t nq = which == 0 ? b->n_fluid : b->n_wall;
+    if (nq == 0) return SPH_OK;
+    hipLaunchKernelGGL((k_neighbours<T, D>), dim3(grid_for(nq)), dim3(kBlock), 0, st, make_par<T>(d),
+                       which, b->n_fluid, b->n_wall, b->key[0], b->pid[0], (const T*)b->off[0],
+                       b->fstart, b->wkey, b->wpid, (const T*)b->woff, b->wstart, offset, count,
+                       list, list_len);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
+// Dispatch on precision and dimension.
+#define SPH_DISPATCH(fn, ...)                                                          \
+    (d->precision == SPH_F32 ? (d->dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)) \
+                             : (d->dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)))
+
+}  // namespace
+
+extern "C" {
+
+int sph_configure(sph_desc* d) {
+    if (!d) return SPH_ERR_ARG;
+    if (d->dim != 2 && d->dim != 3) return SPH_ERR_CONFIG;
+    if (d->precision != SPH_F32 && d->precision != SPH_F64) return SPH_ERR_CONFIG;
+    if (!(d->h > 0.0) || !(d->dx > 0.0) || !(d->c0 > 0.0) || !(d->rho0 > 0.0) || !(d->dt > 0.0))
+        return SPH_ERR_CONFIG;
+    // time step bound, Eqs. (23)-(24) with U_max = c0/10
+    double gn = 0.0;
+    for (int k = 0; k < 3; ++k) gn += d->g[k] * d->g[k];
+    gn = std::sqrt(gn);
+    double dtmax = 0.25 * d->h / (1.1 * d->c0);
+    if (gn > 0.0) dtmax = std::fmin(dtmax, 0.25 * std::sqrt(d->h / gn));
+    if (d->dt > dtmax * (1.0 + 1e-9)) return SPH_ERR_CONFIG;
+    // cell edge: 2h rounded to T, raised until L^2 >= rc2 so that every pair
+    // lies in adjacent cells
+    double L;
+    if (d->precision == SPH_F32) {
+        float Lf = (float)(2.0 * d->h);
+        const float rc2 = (float)(4.0 * d->h * d->h);
+        while (Lf * Lf < rc2 || (double)Lf < 2.0 * d->h) Lf = std::nextafter(Lf, 1e30f);
+        L = Lf;
+    } else {
+        L = 2.0 * d->h;
+    }
+    d->cell = L;
+    int64_t nc = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < d->dim) {
+            if (!(d->hi[k] > d->lo[k])) return SPH_ERR_CONFIG;
+            const double n = std::ceil((d->hi[k] - d->lo[k]) / L);
+            if (n > 1e9) return SPH_ERR_CONFIG;
+            d->grid[k] = (int32_t)(n < 1 ? 1 : n);
+        } else {
+            d->grid[k] = 1;
+        }
+        nc *= d->grid[k];
+        if (nc > (int64_t)INT32_MAX - 2) return SPH_ERR_CONFIG;
+    }
+    d->n_cells = nc;
+    // sigma0: sum_j W over a full lattice of spacing dx around one site
+    const double h = d->h;
+    const double alpha = d->dim == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+    const int R = (int)std::ceil(2.0 * h / d->dx) + 1;
+    const int RZ = d->dim == 3 ? R : 0;
+    double s = 0.0;
+    for (int kz = -RZ; kz <= RZ; ++kz)
+        for (int ky = -R; ky <= R; ++ky)
+            for (int kx = -R; kx <= R; ++kx) {
+                const double q = d->dx * std::sqrt((double)(kx * kx + ky * ky + kz * kz)) / h;
+                if (q < 2.0) {
+                    const double t = 1.0 - 0.5 * q;
+                    s += alpha * t * t * t * t * (1.0 + 2.0 * q);
+                }
+            }
+    d->sigma0 = s;
+    return SPH_OK;
+}
+
+size_t sph_scratch_bytes(const sph_desc* d, int64_t n_fluid, int64_t n_wall) {
+    if (!d || n_fluid < 0 || n_wall < 0) return 0;
+    return layout(d, n_fluid, n_wall, nullptr).bytes;
+}
+
+#define SPH_ENTRY_CHECKS()                 \
+    int rc_ = check_desc(d);               \
+    if (rc_) return rc_;                   \
+    rc_ = check_buf(d, b);                 \
+    if (rc_) return rc_;                   \
+    hipStream_t st = (hipStream_t)stream;
+
+int sph_init(const sph_desc* d, sph_buffers* b, const double* fpos, const double* fvel,
+             const double* frho, const double* wpos, void* stream) {
+    SPH_ENTRY_CHECKS();
+    if (b->n_fluid > 0 && (!fpos || !fvel || !frho)) return SPH_ERR_ARG;
+    if (b->n_wall > 0 && !wpos) return SPH_ERR_ARG;
+    return SPH_DISPATCH(init_t, d, b, fpos, fvel, frho, wpos, st);
+}
+
+int sph_build_cells(const sph_desc* d, sph_buffers* b, void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(build_cells_t, d, b, st);
+}
+
+int sph_density(const sph_desc* d, sph_buffers* b, void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(density_t, d, b, st);
+}
+
+int sph_wall_bc(const sph_desc* d, sph_buffers* b, void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(wall_bc_t, d, b, st);
+}
+
+int sph_forces(const sph_desc* d, sph_buffers* b, unsigned which, void* stream) {
+    SPH_ENTRY_CHECKS();
+    const unsigned kind = which & (SPH_CONTINUITY | SPH_MOMENTUM);
+    if (kind != SPH_CONTINUITY && kind != SPH_MOMENTUM) return SPH_ERR_ARG;
+    if ((which & SPH_NO_KICK) && kind != SPH_MOMENTUM) return SPH_ERR_ARG;
+    if (which & ~(SPH_CONTINUITY | SPH_MOMENTUM | SPH_NO_KICK)) return SPH_ERR_ARG;
+    return SPH_DISPATCH(forces_t, d, b, which, st);
+}
+
+int sph_step(const sph_desc* d, sph_buffers* b, int nsteps, void* stream) {
+    SPH_ENTRY_CHECKS();
+    if (nsteps < 0) return SPH_ERR_ARG;
+    return SPH_DISPATCH(step_t, d, b, nsteps, st);
+}
+
+int sph_diag(const sph_desc* d, sph_buffers* b, void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(diag_t, d, b, st);
+}
+
+int sph_export(const sph_desc* d, const sph_buffers* b, double* pos, double* vel, double* rho,
+               double* acc, void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(export_t, d, b, pos, vel, rho, acc, st);
+}
+
+int sph_export_walls(const sph_desc* d, const sph_buffers* b, double* pw, double* nrm, double* pos,
+                     void* stream) {
+    SPH_ENTRY_CHECKS();
+    return SPH_DISPATCH(export_walls_t, d, b, pw, nrm, pos, st);
+}
+
+int sph_neighbours(const sph_desc* d, const sph_buffers* b, int which, const int64_t* offset,
+                   int32_t* count, int32_t* list, int64_t list_len, void* stream) {
+    SPH_ENTRY_CHECKS();
+    if (which != 0 && which != 1) return SPH_ERR_ARG;
+    if (!count || (list && (!offset || list_len < 0))) return SPH_ERR_ARG;
+    return SPH_DISPATCH(neighbours_t, d, b, which, offset, count, list, list_len, st);
+}
+
+const char* sph_strerror(int code) {
+    switch (code) {
+        case SPH_OK: return "ok";
+        case SPH_ERR_ARG: return "invalid argument (null pointer, size or flag)";
+        case SPH_ERR_CONFIG: return "invalid configuration (dim, precision, grid, or dt above the CFL bound)";
+        case SPH_ERR_LAUNCH: return "kernel launch failed";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+"""HIP path against the FP64 oracle, through the C ABI (needs an MI355X).
+
+Integer results (cell keys, sorted order, cell tables, neighbour pair sets)
+must match bit for bit; fields must match within the scaled tolerances of
+gpu_cases (1e-4 for the FP32 path, 1e-9 for the FP64 path).  Stage tests
+feed the oracle exactly the state the GPU held before the stage.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import (G, TOL32, near_cutoff_scene, pair_set_from_lists, scaled, scales,
+                       small_scenes, tol)
+from paper_2110_02621_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+SMALL = small_scenes()
+
+
+@pytest.fixture(scope="module")
+def solver_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2110_02621_amd import solver
+    return solver
+
+
+def by_pid(raw_pid, values):
+    out = np.empty_like(values)
+    out[raw_pid] = values
+    return out
+
+
+# ---------------------------------------------------------------- sort + pairs
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "near2d", "near3d"])
+def test_pair_sets_and_sort_bitexact(solver_mod, name, prec):
+    sc = near_cutoff_scene(int(name[-2])) if name.startswith("near") else SMALL[name]()
+    print(f"[pairs] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
+    S = solver_mod.Solver(sc, prec)
+    raw = S.raw()
+    dim, nf = sc.dim, sc.n_fluid
+    key = raw["key"][0]
+    # sorted by key, cell table consistent with the keys
+    assert np.all(np.diff(key) >= 0)
+    cnt = np.bincount(key, minlength=int(S.desc.n_cells))
+    assert np.array_equal(raw["fstart"], np.concatenate([[0], np.cumsum(cnt)]))
+    wcnt = np.bincount(raw["wkey"], minlength=int(S.desc.n_cells))
+    assert np.array_equal(raw["wstart"], np.concatenate([[0], np.cumsum(wcnt)]))
+    # stable: from the input order (ids ascending) a stable sort keeps ids
+    # ascending inside each cell
+    start, order = O.counting_sort(key[np.argsort(raw["pid"][0])], int(S.desc.n_cells))
+    assert np.array_equal(raw["pid"][0], order)
+    assert np.array_equal(raw["wpid"], O.counting_sort(raw["wkey"][np.argsort(raw["wpid"])],
+                                                       int(S.desc.n_cells))[1])
+    # pair sets in the kernel's precision
+    single = prec == "f32"
+    L = float(S.desc.cell)
+    rc2 = float(np.float32(4.0 * sc.h * sc.h)) if single else 4.0 * sc.h * sc.h
+    cf, of = S.cell_coords(key), raw["off"][0].T
+    cw, ow = S.cell_coords(raw["wkey"]), raw["woff"].T
+    pid, wpid = raw["pid"][0], raw["wpid"]
+    hff = O.pairs_bruteforce(dim, single, cf, of, cf, of, L, rc2)
+    a, b = np.nonzero(hff)
+    ref = set(zip(pid[a].tolist(), pid[b].tolist()))
+    if sc.n_wall:
+        hfw = O.pairs_bruteforce(dim, single, cf, of, cw, ow, L, rc2)
+        a, b = np.nonzero(hfw)
+        ref |= set(zip(pid[a].tolist(), (nf + wpid[b]).tolist()))
+    got = pair_set_from_lists(*S.neighbours(0))
+    assert got == ref
+    if sc.n_wall:
+        hwf = O.pairs_bruteforce(dim, single, cw, ow, cf, of, L, rc2)
+        a, b = np.nonzero(hwf)
+        ref_w = set(zip(wpid[a].tolist(), pid[b].tolist()))
+        assert pair_set_from_lists(*S.neighbours(1)) == ref_w
+
+
+# ---------------------------------------------------------------- one step, stage by stage
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "dam2d"])
+def test_stage_parity(solver_mod, name, prec):
+    sc = SMALL[name]()
+    print(f"[stage] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
+    sc_ = scales(sc)
+    t = tol(prec)
+    S = solver_mod.Solver(sc, prec, keep_sigma=True)
+    P = O.params_from_scene(sc)
+    e0, w0 = S.export(), S.export_walls()
+    x0, v0, r0, a0 = e0["pos"], e0["vel"], e0["rho"], e0["acc"]
+    wx, wn, pw0 = w0["pos"], w0["nrm"], w0["pw"]
+    errs = {}
+    # init: positions converted to cell + offset
+    errs["x0"] = scaled(x0, sc.fluid_x, sc_["x"])
+    errs["wx"] = scaled(wx, sc.wall_x, sc_["x"])
+    # init: normals (Eq. 16) where they are clearly defined, initial p_w and dv/dt
+    if sc.n_wall:
+        n_o, psi = O.normals(P, wx, with_psi=True)
+        big = np.linalg.norm(psi, axis=1) * sc.h > 1e-3
+        small = np.linalg.norm(psi, axis=1) * sc.h < 1e-6
+        errs["nrm"] = scaled(wn[big], n_o[big], 1.0)
+        assert np.all(wn[small] == 0.0)
+        errs["pw0"] = scaled(pw0, O.wall_pressure(P, wx, x0, r0), sc_["p"])
+    A0 = O.momentum(P, x0, v0, r0, wx, pw0, wn)
+    errs["a0"] = scaled(a0, A0, max(G, np.abs(A0).max()))
+    # density stage: sigma, Eq. (17), half kick, drift
+    S.density()
+    raw = S.raw()
+    pid = raw["pid"][0]
+    sig = by_pid(pid, raw["sigma"])
+    sig_o = O.sigma(P, x0, wx)
+    errs["sigma"] = scaled(sig, sig_o, P.sigma0)
+    rt_o = O.reinit(P, sig_o, r0)
+    rt = by_pid(pid, raw["rho"][raw["sel_rho"]]) + sc.rho0
+    errs["rho_reinit"] = scaled(rt, rt_o, sc_["rho"])
+    errs["p_reinit"] = scaled(sc.c0 ** 2 * (rt - sc.rho0), sc.c0 ** 2 * (rt_o - sc.rho0), sc_["p"])
+    vh_o = v0 + 0.5 * sc.dt * a0
+    vh = by_pid(pid, raw["vel"][raw["sel_vel"]].T)
+    errs["v_half"] = scaled(vh, vh_o, sc_["v"])
+    x1 = by_pid(raw["pid"][1], S.absolute(raw["key"][1], raw["off"][1]))
+    errs["x1"] = scaled(x1, x0 + sc.dt * vh, sc_["x"])
+    # cell build: a stable counting sort of the drifted keys in their prior order
+    S.build_cells()
+    raw2 = S.raw()
+    _, order = O.counting_sort(raw["key"][1], int(S.desc.n_cells))
+    assert np.array_equal(raw2["pid"][0], raw["pid"][1][order])
+    assert np.array_equal(raw2["key"][0], raw["key"][1][order])
+    e1 = S.export()
+    errs["x1_sorted"] = scaled(e1["pos"], x1, sc_["x"])
+    assert np.array_equal(e1["vel"], vh) and np.array_equal(e1["rho"], rt)
+    # wall pressure, Eq. (12)
+    S.wall_bc()
+    pw1 = S.export_walls()["pw"]
+    if sc.n_wall:
+        errs["pw"] = scaled(pw1, O.wall_pressure(P, wx, e1["pos"], e1["rho"]), sc_["p"])
+    # continuity, Eqs. (9), (21)
+    S.continuity()
+    e2 = S.export()
+    D_o = O.continuity(P, e1["pos"], e1["vel"], e1["rho"], wx, pw1)
+    errs["rho_new"] = scaled(e2["rho"], e1["rho"] + sc.dt * D_o, sc_["rho"])
+    errs["p_new"] = scaled(sc.c0 ** 2 * (e2["rho"] - sc.rho0),
+                           sc.c0 ** 2 * (e1["rho"] + sc.dt * D_o - sc.rho0), sc_["p"])
+    if prec == "f64":
+        errs["drho_dt"] = scaled((e2["rho"] - e1["rho"]) / sc.dt, D_o, np.abs(D_o).max() + 1e-30) * 1e-3
+    # momentum, Eqs. (10)-(11), (13)-(15), (22)
+    S.momentum()
+    e3 = S.export()
+    A_o = O.momentum(P, e1["pos"], e1["vel"], e2["rho"], wx, pw1, wn)
+    errs["acc"] = scaled(e3["acc"], A_o, max(G, np.abs(A_o).max()))
+    errs["v_new"] = scaled(e3["vel"], e1["vel"] + 0.5 * sc.dt * A_o, sc_["v"])
+    st = S.status()
+    print("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), st, flush=True)
+    assert st["out_of_grid"] == 0 and st["fast"] == 0
+    bad = {k: v for k, v in errs.items() if not v <= t}
+    assert not bad, bad
+
+
+# ---------------------------------------------------------------- trajectories
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["dam3d", "dam2d"])
+def test_trajectory_steps_1_10_100(solver_mod, name, prec):
+    sc = SMALL[name]()
+    print(f"[traj] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
+    s = scales(sc)
+    S = solver_mod.Solver(sc, prec)
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+    done = 0
+    for n in (1, 10, 100):
+        S.step(n - done)
+        st.step(n - done)
+        done = n
+        e = S.export()
+        errs = dict(x=scaled(e["pos"], st.x, s["x"]), v=scaled(e["vel"], st.v, s["v"]),
+                    p=scaled(sc.c0 ** 2 * (e["rho"] - sc.rho0), sc.c0 ** 2 * (st.rho - sc.rho0), s["p"]),
+                    a=scaled(e["acc"], st.a, max(G, np.abs(st.a).max())),
+                    pw=scaled(S.export_walls()["pw"], st.pw, s["p"]))
+        print(f"  step {n}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        bad = {k: v for k, v in errs.items() if not v <= tol(prec)}
+        assert not bad, (n, bad)
+    d = S.diag()
+    od = st.diag()
+    assert d["M"] == pytest.approx(od["M"], rel=1e-12)
+    assert d["steps"] == 100
+    assert S.status() == dict(out_of_grid=0, fast=0, nonfinite=0)
+
+
+def test_hydrostatic_tank_fp64(solver_mod):
+    # 2-D tank at rest (dx = 0.025, H = 1), pre-relaxed by the oracle; 200
+    # FP64 GPU steps match 200 oracle steps and keep p within 5 % of
+    # rho0 g (H - z).
+    sc = scenes.hydrostatic_tank_2d()
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+    st.step(3000, damp=0.03)
+    relaxed = sc.with_params(fluid_x=st.x.copy(), fluid_v=np.zeros_like(st.v), fluid_rho=st.rho.copy())
+    ref = O.State(P, relaxed.fluid_x, relaxed.fluid_v, relaxed.fluid_rho, relaxed.wall_x).step(200)
+    S = solver_mod.Solver(relaxed, "f64")
+    S.step(200)
+    e = S.export()
+    s = scales(sc)
+    assert scaled(e["pos"], ref.x, s["x"]) < 1e-9
+    assert scaled(sc.c0 ** 2 * (e["rho"] - sc.rho0), sc.c0 ** 2 * (ref.rho - sc.rho0), s["p"]) < 1e-9
+    p = sc.c0 ** 2 * (e["rho"] - sc.rho0)
+    pa = sc.rho0 * G * (sc.H - e["pos"][:, 1])
+    ep = np.linalg.norm(p - pa) / np.linalg.norm(pa)
+    print(f"  e_p = {ep:.4f}", flush=True)
+    assert ep < 5e-2
+
+
+def test_determinism_bitwise(solver_mod):
+    sc = SMALL["dam3d"]()
+    outs = []
+    for _ in range(2):
+        S = solver_mod.Solver(sc, "f32")
+        S.step(20)
+        outs.append((S.export(), S.export_walls(), S.raw()))
+    for k in ("pos", "vel", "rho", "acc"):
+        assert np.array_equal(outs[0][0][k], outs[1][0][k]), k
+    assert np.array_equal(outs[0][1]["pw"], outs[1][1]["pw"])
+    assert np.array_equal(outs[0][2]["pid"], outs[1][2]["pid"])
+
+
+def test_diag_and_probe(solver_mod):
+    sc = scenes.dam_break_2d(dx=0.02, steps=50)
+    assert len(sc.probe) == 5
+    S = solver_mod.Solver(sc, "f64")
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe)
+    S.step(50)
+    st.step(50)
+    d, od = S.diag(), st.diag()
+    e = S.export()
+    od2 = O.diag(P, e["pos"], e["vel"])
+    assert d["M"] == pytest.approx(od2["M"], rel=1e-14)
+    assert d["Ek"] == pytest.approx(od2["Ek"], rel=1e-12)
+    assert d["Ep"] == pytest.approx(od2["Ep"], rel=1e-12)
+    assert d["vmax"] == pytest.approx(od2["vmax"], rel=1e-14)
+    assert np.allclose(d["P"][:2], od2["P"][:2], rtol=1e-10, atol=1e-12 * od2["M"])
+    assert d["J"] == pytest.approx(st.J, rel=1e-9)
+    assert st.J > 0
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_no_fluid(solver_mod):
+    sc = SMALL["dam2d"]()
+    sc = sc.with_params(fluid_x=np.zeros((0, 2)), fluid_v=np.zeros((0, 2)), fluid_rho=np.zeros(0))
+    S = solver_mod.Solver(sc, "f32")
+    S.step(3)
+    w = S.export_walls()
+    assert np.all(w["pw"] == 0.0)
+    assert S.diag()["M"] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_edge_free_fall_no_walls(solver_mod, prec):
+    # isolated particle: kick-drift-kick integrates g exactly (Sec. 2.6)
+    sc = scenes.random_box(dim=3, n=1, seed=3, walls=False)
+    x0 = np.array([[0.05, 0.05, 0.6]])
+    v0 = np.array([[0.1, -0.2, 0.3]])
+    sc = sc.with_params(fluid_x=x0, fluid_v=v0, fluid_rho=np.array([1000.0]), hi=np.array([0.2, 0.2, 0.7]),
+                        lo=np.array([-0.1, -0.1, -0.1]))
+    S = solver_mod.Solver(sc, prec)
+    S.step(100)
+    t = 100 * sc.dt
+    e = S.export()
+    ref = x0 + v0 * t + 0.5 * np.array([0, 0, -G]) * t * t
+    tol_x = 1e-12 if prec == "f64" else 2e-6
+    assert np.abs(e["pos"] - ref).max() < tol_x
+    assert e["rho"][0] == pytest.approx(1000.0, rel=1e-6)
+
+
+def test_edge_leaving_grid_is_counted(solver_mod):
+    sc = scenes.random_box(dim=3, n=1, seed=3, walls=False)
+    sc = sc.with_params(fluid_x=np.array([[0.05, 0.05, 0.1]]), fluid_v=np.array([[0.0, 0.0, 5.0]]),
+                        fluid_rho=np.array([1000.0]), hi=np.array([0.2, 0.2, 0.12]),
+                        lo=np.array([-0.1, -0.1, -0.1]))
+    S = solver_mod.Solver(sc, "f32")
+    S.step(60)
+    st = S.status()
+    assert st["out_of_grid"] > 0
+    e = S.export()
+    assert np.all(e["pos"][:, 2] <= -0.1 + float(S.desc.grid[2]) * float(S.desc.cell))
+
+
+def test_edge_time_step_above_cfl_rejected(solver_mod):
+    from paper_2110_02621_amd.abi import SPHError
+    sc = SMALL["box3d"]()
+    with pytest.raises(SPHError):
+        solver_mod.Solver(sc.with_params(dt=2 * sc.dt), "f32")
+
+
+def test_edge_coincident_particles(solver_mod):
+    # two particles at the same point: r = 0 pairs add W(0) to sigma and
+    # nothing to the gradient sums (no NaN)
+    sc = SMALL["box3d"]()
+    x = sc.fluid_x.copy()
+    x[1] = x[0]
+    sc = sc.with_params(fluid_x=x)
+    S = solver_mod.Solver(sc, "f32")
+    S.step(2)
+    e = S.export()
+    assert np.all(np.isfinite(e["acc"])) and np.all(np.isfinite(e["rho"]))
