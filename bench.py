@@ -91,16 +91,10 @@ def timed_run(solver_mod, scene, precision, steps, warmup):
 def pair_counts(S):
     """Interacting pairs of the current state: fluid-fluid (self excluded),
     fluid-wall, wall-fluid, and fluid-(fluid+wall) with self."""
-    import torch
+    c = S.pair_counts()
     nf = S.scene.n_fluid
-    cnt, off, lst = S.neighbours(0)
-    lst_t = torch.as_tensor(lst)
-    fw = int((lst_t >= nf).sum())
-    total = int(cnt.astype("int64").sum())
-    ff = total - fw - nf
-    wcnt, _, _ = S.neighbours(1)
-    del lst, lst_t
-    return dict(ff=ff, fw=fw, wf=int(wcnt.astype("int64").sum()), all_with_self=total)
+    return dict(ff=c["ff_with_self"] - nf, fw=c["fw"], wf=c["wf"],
+                all_with_self=c["ff_with_self"] + c["fw"], max_ff=c["max_ff"])
 
 
 def main():

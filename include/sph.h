@@ -60,6 +60,8 @@ extern "C" {
 #define SPH_STATUS_OUT_OF_GRID 0 /* particle steps whose drift left the cell grid (clamped) */
 #define SPH_STATUS_FAST 1        /* drifts longer than one cell per step (CFL violated) */
 #define SPH_STATUS_NONFINITE 2   /* non-finite values met by sph_diag */
+#define SPH_STATUS_LIST_OVERFLOW 3 /* particles with more neighbours than a list holds (those
+                                      sweep the cells instead: slower, same result) */
 #define SPH_STATUS_LEN 4
 
 /* Diagnostics written by sph_diag (double[SPH_DIAG_LEN], device). */
@@ -132,6 +134,18 @@ typedef struct sph_buffers {
     const int32_t *probe;  /* optional: wall ids of the probe patch (device) */
     int32_t n_probe;
     int32_t reserved;
+    /* Optional neighbour lists (all three or none).  When given,
+     * sph_build_cells fills them for the sorted state and every sweep reads
+     * them instead of walking the cells (same pairs, same order, same
+     * arithmetic).  Entry k of query q is list[k * n_query + q]: the sorted
+     * index of the neighbour in the low 26 bits, the cell shift + 1 per axis
+     * in two bits each above (n_fluid, n_wall < 2^26).  count[q] holds the
+     * full neighbour count, which may exceed cap. */
+    uint32_t *nbr_ff;  /* fluid -> fluid, uint32[cap_ff][n_fluid] */
+    uint32_t *nbr_fw;  /* fluid -> wall, uint32[cap_fw][n_fluid] */
+    uint32_t *nbr_wf;  /* wall -> fluid, uint32[cap_wf][n_wall] */
+    int32_t *cnt_ff, *cnt_fw, *cnt_wf;
+    int32_t cap_ff, cap_fw, cap_wf, reserved3;
 } sph_buffers;
 
 /* Validates the run description and fills its derived fields: L_c = 2h
@@ -165,7 +179,8 @@ int sph_init(const sph_desc *desc, sph_buffers *buf, const double *fpos, const d
  * Stable counting sort of the drifted fluid (key[1], off[1], pid[1] and the
  * current velocity and density) by cell key into key[0], off[0], pid[0] and
  * the other velocity/density copy; particles of one cell keep their prior
- * order.  Rebuilds fstart.  Swaps sel_vel and sel_rho. */
+ * order.  Rebuilds fstart and, if present, the neighbour lists.  Swaps
+ * sel_vel and sel_rho. */
 int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Density update (Sec. 2.5 and 2.6): at the current positions
@@ -226,6 +241,89 @@ int sph_export_walls(const sph_desc *desc, const sph_buffers *buf, double *pw, d
  * entries that would fall outside [0, list_len) are dropped. */
 int sph_neighbours(const sph_desc *desc, const sph_buffers *buf, int which, const int64_t *offset,
                    int32_t *count, int32_t *list, int64_t list_len, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Adjoint: reverse-mode derivatives of a probe functional               */
+/*   J = sum over steps of dt * mean(p_w over the probe walls)           */
+/* with respect to theta = (mu, gamma_p, c0, H), H the initial column    */
+/* height (the fluid is stretched vertically, masses unchanged, with the  */
+/* hydrostatic initial density).  The backward follows the forward step  */
+/* in reverse: momentum and second kick, continuity and density update,  */
+/* wall pressure, drift, half kick, reinitialisation, number density.    */
+/* Cell keys, sorted order and neighbour sets are taken from the forward */
+/* frames (recomputed bit for bit, not differentiated); branches (the    */
+/* limiter, max() of Eq. (17), delta < 1) take the forward's side, with  */
+/* derivative 0 at max(x, 0)'s kink.  The adjoint runs in FP64.          */
+/* ------------------------------------------------------------------ */
+
+#define SPH_THETA_MU 0
+#define SPH_THETA_GAMMA 1
+#define SPH_THETA_C0 2
+#define SPH_THETA_H 3
+#define SPH_NTHETA 4
+
+/* What the backward of a step needs from the forward, for the state at
+ * r^n (device arrays in that state's sorted order, T as in sph_buffers).
+ * Frame n+1 carries the quantities step n computed at r^{n+1}. */
+typedef struct sph_frame {
+    const int32_t *key, *pid; /* sorted state at r^n */
+    const void *off;          /* T[dim][n_fluid] */
+    const int32_t *fstart;    /* cell table of this state (n_cells + 1) */
+    const void *rho;          /* T[n_fluid] rho^n - rho0 */
+    const void *sigma;        /* T[n_fluid] sigma at r^n (from step n's density update) */
+    const void *vh;           /* T[dim][n_fluid] velocity of the drift into r^n (frame 0: v^0) */
+    const void *rt;           /* T[n_fluid] reinitialised density of step n-1, minus rho0 */
+    const void *pw;           /* T[n_wall] wall pressure at r^n (frame 0: the initial one) */
+} sph_frame;
+
+/* Adjoint state (device, FP64, particle-id order) and workspace. */
+typedef struct sph_adjoint {
+    double *xb;    /* [dim][n_fluid] dJ/dr */
+    double *vb;    /* [dim][n_fluid] dJ/dv */
+    double *rhob;  /* [n_fluid]      dJ/drho */
+    double *ab;    /* [dim][n_fluid] dJ/d(dv/dt) carried by the half kick */
+    double *theta; /* [SPH_NTHETA] accumulated dJ/dtheta */
+    void *work;    /* >= sph_adjoint_work_bytes(...), 256-byte aligned */
+    size_t work_bytes;
+} sph_adjoint;
+
+size_t sph_adjoint_work_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
+
+/* Zeroes the adjoint state and theta. */
+int sph_adjoint_zero(const sph_desc *desc, const sph_buffers *buf, sph_adjoint *adj, void *stream);
+
+/* Backward of the momentum sweep with the second kick (Eqs. (10)-(11),
+ * (13)-(15), (22)) and of the continuity sweep with the density update
+ * (Eqs. (9), (21)) of step n, at the state of frame next = n+1.  Consumes
+ * the adjoint of (v^{n+1}, rho^{n+1}, dv/dt^{n+1}); leaves the adjoints of
+ * the half-step velocity and the reinitialised density in the workspace and
+ * adds to dJ/dr^{n+1}, dJ/dmu, dJ/dgamma_p, dJ/dc0.  buf supplies the walls
+ * (sorted once), the probe and nothing else. */
+int sph_forces_bwd(const sph_desc *desc, const sph_buffers *buf, const sph_frame *next,
+                   sph_adjoint *adj, void *stream);
+
+/* Backward of the wall pressure, Eq. (12), of step n at frame next,
+ * including the probe functional's own dt * mean(p_w) term. */
+int sph_wall_bc_bwd(const sph_desc *desc, const sph_buffers *buf, const sph_frame *next,
+                    sph_adjoint *adj, void *stream);
+
+/* Backward of the drift, the half kick and the reinitialisation of Eq. (17)
+ * with the number density sweep of step n, at frame cur = n (positions
+ * r^n).  Leaves the adjoint of the state at step n in adj. */
+int sph_density_bwd(const sph_desc *desc, const sph_buffers *buf, const sph_frame *cur,
+                    sph_adjoint *adj, void *stream);
+
+/* One full step backward: sph_forces_bwd and sph_wall_bc_bwd at next,
+ * then sph_density_bwd at cur. */
+int sph_step_bwd(const sph_desc *desc, const sph_buffers *buf, const sph_frame *cur,
+                 const sph_frame *next, sph_adjoint *adj, void *stream);
+
+/* Backward of sph_init's initial wall pressure and dv/dt at frame 0, then
+ * of the initial state itself: adds dJ/dH (vertical stretch of the fluid
+ * column of height H above the floor z = 0, hydrostatic initial density)
+ * and the initial density's share of dJ/dc0. */
+int sph_init_bwd(const sph_desc *desc, const sph_buffers *buf, const sph_frame *f0, double H,
+                 sph_adjoint *adj, void *stream);
 
 /* Static text for a return code. */
 const char *sph_strerror(int code);

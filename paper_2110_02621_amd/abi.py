@@ -14,13 +14,16 @@ LIB_PATH = os.path.join(HERE, "libsph.so")
 SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH = 0, 1, 2, 3
 SPH_F32, SPH_F64 = 0, 1
 SPH_CONTINUITY, SPH_MOMENTUM, SPH_NO_KICK = 1, 2, 4
-SPH_STATUS_OUT_OF_GRID, SPH_STATUS_FAST, SPH_STATUS_NONFINITE, SPH_STATUS_LEN = 0, 1, 2, 4
+SPH_STATUS_OUT_OF_GRID, SPH_STATUS_FAST, SPH_STATUS_NONFINITE, SPH_STATUS_LIST_OVERFLOW = 0, 1, 2, 3
+SPH_STATUS_LEN = 4
 SPH_DIAG_MASS, SPH_DIAG_MOM, SPH_DIAG_EKIN, SPH_DIAG_EPOT = 0, 1, 4, 5
 SPH_DIAG_VMAX, SPH_DIAG_PROBE, SPH_DIAG_STEPS, SPH_DIAG_LEN = 6, 7, 8, 16
 
 EXPORTED = ["sph_configure", "sph_scratch_bytes", "sph_init", "sph_build_cells", "sph_density",
             "sph_wall_bc", "sph_forces", "sph_step", "sph_diag", "sph_export", "sph_export_walls",
-            "sph_neighbours", "sph_strerror"]
+            "sph_neighbours", "sph_strerror",
+            "sph_adjoint_work_bytes", "sph_adjoint_zero", "sph_forces_bwd", "sph_wall_bc_bwd",
+            "sph_density_bwd", "sph_step_bwd", "sph_init_bwd"]
 
 
 class Desc(C.Structure):
@@ -47,6 +50,9 @@ class Buffers(C.Structure):
         ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t),
         ("status", C.c_void_p), ("diag", C.c_void_p), ("sigma_out", C.c_void_p),
         ("probe", C.c_void_p), ("n_probe", C.c_int32), ("reserved", C.c_int32),
+        ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
+        ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p),
+        ("cap_ff", C.c_int32), ("cap_fw", C.c_int32), ("cap_wf", C.c_int32), ("reserved3", C.c_int32),
     ]
 
 

@@ -1,0 +1,207 @@
+"""Reverse-through-time derivatives of the wall-probe functional
+
+    J = sum over steps n of dt * mean(p_w^n over the probe walls)
+
+with respect to theta = (mu, gamma_p, c0, H) on the GPU.  The forward runs
+the C-ABI step with checkpoints every K steps; the backward restores each
+checkpoint in reverse, recomputes its K steps (bit for bit: same kernels,
+same inputs) keeping one frame per step, and runs the hand-written backward
+kernels (``sph_step_bwd``), ending with the initial state
+(``sph_init_bwd``).  ``ProbeFunctional`` wraps both as a
+``torch.autograd.Function`` of theta.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import abi, scenes
+from .abi import check
+from .solver import Solver, _p
+
+THETA_NAMES = ("mu", "gamma_p", "c0", "H")
+
+
+class Frame(C.Structure):
+    _fields_ = [("key", C.c_void_p), ("pid", C.c_void_p), ("off", C.c_void_p), ("fstart", C.c_void_p),
+                ("rho", C.c_void_p), ("sigma", C.c_void_p), ("vh", C.c_void_p), ("rt", C.c_void_p),
+                ("pw", C.c_void_p)]
+
+
+class Adjoint(C.Structure):
+    _fields_ = [("xb", C.c_void_p), ("vb", C.c_void_p), ("rhob", C.c_void_p), ("ab", C.c_void_p),
+                ("theta", C.c_void_p), ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+
+
+def _declare(L):
+    if getattr(L, "_adjoint_declared", False):
+        return
+    dp, bp = C.POINTER(abi.Desc), C.POINTER(abi.Buffers)
+    fp, ap = C.POINTER(Frame), C.POINTER(Adjoint)
+    vp = C.c_void_p
+    L.sph_adjoint_work_bytes.argtypes = [dp, C.c_int64, C.c_int64]
+    L.sph_adjoint_work_bytes.restype = C.c_size_t
+    L.sph_adjoint_zero.argtypes = [dp, bp, ap, vp]
+    for name in ("sph_forces_bwd", "sph_wall_bc_bwd", "sph_density_bwd"):
+        getattr(L, name).argtypes = [dp, bp, fp, ap, vp]
+    L.sph_step_bwd.argtypes = [dp, bp, fp, fp, ap, vp]
+    L.sph_init_bwd.argtypes = [dp, bp, fp, C.c_double, ap, vp]
+    for name in ("sph_adjoint_zero", "sph_forces_bwd", "sph_wall_bc_bwd", "sph_density_bwd",
+                 "sph_step_bwd", "sph_init_bwd"):
+        getattr(L, name).restype = C.c_int
+    L._adjoint_declared = True
+
+
+def _cur(S):
+    """Views of the solver's current sorted state and fields."""
+    t, b = S.t, S.buf
+    return dict(key=t["key"][0], pid=t["pid"][0], off=t["off"][0], fstart=t["fstart"],
+                vel=t["vel"][b.sel_vel], rho=t["rho"][b.sel_rho], acc=t["acc"], pw=t["pw"])
+
+
+def save_state(S):
+    """Everything needed to resume the forward from here (device copies)."""
+    c = _cur(S)
+    st = {k: c[k].clone() for k in ("key", "pid", "off", "fstart", "vel", "rho", "acc", "pw")}
+    for k in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
+        st[k] = S.t[k].clone()
+    return st
+
+
+def load_state(S, st):
+    c = _cur(S)
+    for k in ("key", "pid", "off", "fstart", "vel", "rho", "acc", "pw"):
+        c[k].copy_(st[k])
+    for k in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
+        S.t[k].copy_(st[k])
+
+
+class FrameStore:
+    """Per-step frames of one recomputed segment (device tensors)."""
+
+    def __init__(self):
+        self.t = {}
+
+    def struct(self):
+        f = Frame()
+        for name, _ in Frame._fields_:
+            v = self.t.get(name)
+            setattr(f, name, _p(v).value if v is not None else None)
+        return f
+
+
+def recompute_segment(S, start_state, nsteps, first_frame_extra=None):
+    """Restore `start_state`, run nsteps steps stage by stage and return the
+    nsteps + 1 frames (frame k = state at step start + k)."""
+    load_state(S, start_state)
+    frames = [FrameStore() for _ in range(nsteps + 1)]
+    f0 = frames[0].t
+    for k in ("key", "pid", "off", "fstart", "rho"):
+        f0[k] = start_state[k]
+    if first_frame_extra:
+        f0.update(first_frame_extra)
+    for n in range(nsteps):
+        S.density()
+        frames[n].t["sigma"] = S.t["sigma"].clone()
+        S.build_cells()
+        c = _cur(S)
+        nxt = frames[n + 1].t
+        for k in ("key", "pid", "off", "fstart"):
+            nxt[k] = c[k].clone()
+        nxt["vh"] = c["vel"].clone()
+        nxt["rt"] = c["rho"].clone()
+        S.wall_bc()
+        nxt["pw"] = S.t["pw"].clone()
+        S.continuity()
+        nxt["rho"] = _cur(S)["rho"].clone()
+        S.momentum()
+    return frames
+
+
+def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", return_timings=False):
+    """J and dJ/dtheta for theta = (mu, gamma_p, c0, H) of `scene` over
+    `steps` steps (default scene.steps), checkpoints every K steps."""
+    import time
+    steps = scene.steps if steps is None else steps
+    S = Solver(scene, precision, device=device, probe=True, keep_sigma=True)
+    L = S.lib
+    _declare(L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    # forward with checkpoints
+    init_extra = dict(vh=_cur(S)["vel"].clone(), pw=S.t["pw"].clone())
+    ckpts = []
+    done = 0
+    while done < steps:
+        ckpts.append((done, save_state(S)))
+        k = min(K, steps - done)
+        S.step(k)
+        done += k
+    J = S.diag()["J"]
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # backward
+    nf, nw, dim = scene.n_fluid, scene.n_wall, scene.dim
+    dev = S.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    A = {k: torch.zeros((dim, nf) if k != "rhob" else (nf,), **f64) for k in ("xb", "vb", "rhob", "ab")}
+    theta = torch.zeros(abi.SPH_DIAG_LEN, **f64)[:4]
+    wb = int(L.sph_adjoint_work_bytes(C.byref(S.desc), nf, nw))
+    work = torch.zeros(wb + 256, dtype=torch.uint8, device=dev)
+    adj = Adjoint()
+    adj.xb, adj.vb, adj.rhob, adj.ab = (_p(A[k]).value for k in ("xb", "vb", "rhob", "ab"))
+    adj.theta = _p(theta).value
+    adj.work = (work.data_ptr() + 255) & ~255
+    adj.work_bytes = wb
+    stream = S._stream()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    check(L.sph_adjoint_zero(C.byref(S.desc), C.byref(S.buf), C.byref(adj), stream), "sph_adjoint_zero")
+    for seg in reversed(range(len(ckpts))):
+        start, st = ckpts[seg]
+        k = min(K, steps - start)
+        frames = recompute_segment(S, st, k, init_extra if start == 0 else None)
+        structs = [f.struct() for f in frames]
+        for n in reversed(range(k)):
+            check(L.sph_step_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[n]),
+                                 C.byref(structs[n + 1]), C.byref(adj), stream), "sph_step_bwd")
+        if start == 0:
+            check(L.sph_init_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[0]), float(scene.H),
+                                 C.byref(adj), stream), "sph_init_bwd")
+        del frames, structs
+    grad = theta.cpu().numpy().copy()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t1
+    out = dict(J=J, grad=dict(zip(THETA_NAMES, grad.tolist())), status=S.status())
+    if return_timings:
+        out["t_forward"] = t_fwd
+        out["t_backward"] = t_bwd
+    return out
+
+
+def scene_for(theta, base="dam_break_2d", **kw):
+    """The scene of a parameter vector theta = (mu, gamma_p, c0, H)."""
+    mu, gp, c0, H = (float(x) for x in theta)
+    if base == "dam_break_2d":
+        return scenes.dam_break_2d(mu=mu, gamma_p=gp, c0=c0, column_height=H, **kw)
+    raise ValueError(base)
+
+
+class ProbeFunctional(torch.autograd.Function):
+    """J(theta) of the 2-D dam break with its hand-written adjoint.
+
+    forward(theta: float64 tensor [mu, gamma_p, c0, H], precision, K, scene kwargs)"""
+
+    @staticmethod
+    def forward(ctx, theta, precision="f32", K=50, scene_kw=None):
+        sc = scene_for(theta.detach().cpu().numpy(), **(scene_kw or {}))
+        r = probe_gradient(sc, precision=precision, K=K)
+        g = torch.tensor([r["grad"][n] for n in THETA_NAMES], dtype=torch.float64)
+        ctx.save_for_backward(g)
+        return torch.tensor(r["J"], dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return gJ * g.to(gJ.device), None, None, None

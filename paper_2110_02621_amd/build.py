@@ -10,8 +10,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "sph_kernels.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", "sph_device.h"), os.path.join(ROOT, "include", "sph.h")]
+SRC = [os.path.join(HERE, "csrc", "sph_kernels.hip"), os.path.join(HERE, "csrc", "sph_adjoint.hip")]
+DEPS = SRC + [os.path.join(HERE, "csrc", n) for n in ("sph_device.h", "sph_host.h")] + \
+    [os.path.join(ROOT, "include", "sph.h")]
 LIB = os.path.join(HERE, "libsph.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -95,11 +95,21 @@ __device__ __forceinline__ void cell_of(const Par<T>& P, int key, int c[3]) {
     c[2] = t / P.ny;
 }
 
+// Neighbour list entries: index j in the low 26 bits, the cell shift
+// c_j - c_i + 1 per axis in two bits each above it.
+constexpr uint32_t kIdxBits = 26;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+
+__device__ __forceinline__ uint32_t shift_code(int sx, int sy, int sz) {
+    return (uint32_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4)) << kIdxBits;
+}
+
 // Visit every particle j of a cell-sorted set with |r_i - r_j|^2 < rc2,
 // for a query point in cell c with offset oi.  The x-neighbours of a cell
 // are adjacent in key order, so each (y, z) row of 3 cells is one
 // contiguous index range; the cell of j inside the row follows from the
-// row's cell starts.  f(j, d, r2) receives d = r_i - r_j.
+// row's cell starts.  f(j, d, r2, code) receives d = r_i - r_j and the
+// shift code of the pair.
 template <typename T, int D, typename F>
 __device__ __forceinline__ void for_neighbours(const Par<T>& P, const int32_t* __restrict__ start,
                                                const T* __restrict__ o0, const T* __restrict__ o1,
@@ -113,19 +123,66 @@ __device__ __forceinline__ void for_neighbours(const Par<T>& P, const int32_t* _
         const T sz = T(z - c[2]) * P.L;
         for (int y = ylo; y <= yhi; ++y) {
             const T sy = T(y - c[1]) * P.L;
+            const uint32_t cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
             const int row = P.nx * (y + P.ny * z);
             const int j0 = start[row + xlo];
             const int jm = start[row + c[0]];
             const int jp = start[row + c[0] + 1];
             const int j1 = start[row + xhi + 1];
             for (int j = j0; j < j1; ++j) {
-                const T sx = j < jm ? -P.L : (j < jp ? T(0) : P.L);
+                const int ix = j < jm ? -1 : (j < jp ? 0 : 1);
+                const T sx = T(ix) * P.L;
                 T d[3];
                 const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), sx, sy, sz, d);
-                if (r2 < P.rc2) f(j, d, r2);
+                if (r2 < P.rc2) f(j, d, r2, cyz | ((uint32_t)(ix + 1) << kIdxBits));
             }
         }
     }
+}
+
+// Neighbour list of one query particle: entry k at list[k * stride + i]
+// (interleaved: a wave reads one entry of 64 particles in one coalesced
+// access).  The distance is recomputed exactly as in the cell walk, so a
+// sweep over the list sees bit-identical d and r^2, in the same order.
+struct NbrList {
+    const uint32_t* list;  // null: no list, walk the cells
+    const int32_t* count;
+    int64_t stride;
+    int cap;
+};
+
+template <typename T, int D, typename F>
+__device__ __forceinline__ void for_list(const Par<T>& P, const uint32_t* __restrict__ list,
+                                         int64_t stride, int64_t i, int n,
+                                         const T* __restrict__ o0, const T* __restrict__ o1,
+                                         const T* __restrict__ o2, const T oi[3], F&& f) {
+    for (int k = 0; k < n; ++k) {
+        const uint32_t e = list[(int64_t)k * stride + i];
+        const int j = (int)(e & kIdxMask);
+        const T sx = T((int)((e >> 26) & 3u) - 1) * P.L;
+        const T sy = T((int)((e >> 28) & 3u) - 1) * P.L;
+        const T sz = T((int)((e >> 30) & 3u) - 1) * P.L;
+        T d[3];
+        const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), sx, sy, sz, d);
+        f(j, d, r2, e & ~kIdxMask);
+    }
+}
+
+// The neighbours of query i: from its list when one exists and did not
+// overflow, else by walking the cells.
+template <typename T, int D, typename F>
+__device__ __forceinline__ void visit(const Par<T>& P, const NbrList& NL, int64_t i,
+                                      const int32_t* __restrict__ start, const T* __restrict__ o0,
+                                      const T* __restrict__ o1, const T* __restrict__ o2,
+                                      const int c[3], const T oi[3], F&& f) {
+    if (NL.list) {
+        const int n = NL.count[i];
+        if (n <= NL.cap) {
+            for_list<T, D>(P, NL.list, NL.stride, i, n, o0, o1, o2, oi, f);
+            return;
+        }
+    }
+    for_neighbours<T, D>(P, start, o0, o1, o2, c, oi, f);
 }
 
 // Quintic Wendland C2 (kappa = 2) at r: q = r/h, t = 1 - q/2,

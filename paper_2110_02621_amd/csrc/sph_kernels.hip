@@ -28,6 +28,7 @@
 
 #include "sph.h"
 #include "sph_device.h"
+#include "sph_host.h"
 
 using namespace sph;
 
@@ -37,7 +38,6 @@ namespace {
 // Small helpers
 // ---------------------------------------------------------------------------
 
-inline int grid_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,9 +67,6 @@ __global__ void __launch_bounds__(kBlock) k_hist(const int32_t* __restrict__ key
     if (i < n) slot[i] = atomicAdd(&count[key[i]], 1);
 }
 
-constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 4;
-constexpr int kScanTile = kScanThreads * kScanPer;
 
 // Exclusive scan of one value per thread over a block of kScanThreads.
 __device__ __forceinline__ int block_exclusive_scan(int v, int* waves, int& total) {
@@ -215,12 +212,6 @@ __global__ void __launch_bounds__(kBlock)
 // Position conversion: absolute double -> cell + offset in T.
 // ---------------------------------------------------------------------------
 
-struct GridD {
-    double lo[3];
-    double L;
-    int n[3];
-};
-
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_to_cells(const double* __restrict__ pos, int64_t n, GridD G, int32_t* __restrict__ key,
@@ -283,7 +274,7 @@ __global__ void __launch_bounds__(kBlock)
     cell_of(P, wkey[w], c);
     const T oi[3] = {o0[w], o1[w], D == 3 ? o2[w] : T(0)};
     T psi[3] = {0, 0, 0};
-    for_neighbours<T, D>(P, wstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+    for_neighbours<T, D>(P, wstart, o0, o1, o2, c, oi, [&](int, const T d[3], T r2, uint32_t) {
         if (r2 > T(0)) {
             const T F = wendland_F(P, root(r2));
 #pragma unroll
@@ -348,7 +339,7 @@ __device__ __forceinline__ int renormalise(T& o, T L, uint32_t* status) {
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_density(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_density(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
               const int32_t* __restrict__ pid, const T* __restrict__ off,
               const int32_t* __restrict__ fstart, const T* __restrict__ woff,
               const int32_t* __restrict__ wstart, T* __restrict__ vel, T* __restrict__ drho,
@@ -364,9 +355,9 @@ __global__ void __launch_bounds__(kBlock)
     cell_of(P, key[i], c);
     const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
     T s = T(0), comp = T(0);
-    auto addW = [&](int, const T*, T r2) { kahan_add(s, comp, wendland_W(P, root(r2))); };
-    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, addW);
-    if (nw > 0) for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
+    auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, root(r2))); };
+    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, addW);
+    if (nw > 0) visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
     if (sigma_out) sigma_out[i] = s;
     // Eq. (17) in deviations from rho0: rho_s - rho0 = rho0 (sigma - sigma0)/sigma0.
     const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
@@ -406,7 +397,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_wall_bc(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+    k_wall_bc(Par<T> P, NbrList LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
               const T* __restrict__ woff, const T* __restrict__ off,
               const int32_t* __restrict__ fstart, const T* __restrict__ drho, T* __restrict__ pw) {
     const int64_t w = global_index();
@@ -416,8 +407,8 @@ __global__ void __launch_bounds__(kBlock)
     const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
     T sW = T(0), sP = T(0), sR[3] = {0, 0, 0};
     if (nf > 0)
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow,
-                             [&](int f, const T d[3], T r2) {
+        visit<T, D>(P, LWF, w, fstart, off, off + nf, off + 2 * nf, c, ow,
+                             [&](int f, const T d[3], T r2, uint32_t) {
                                  const T W = wendland_W(P, root(r2));
                                  const T dr = drho[f];
                                  sW += W;
@@ -462,7 +453,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_continuity(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_continuity(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                  const T* __restrict__ off, const int32_t* __restrict__ fstart,
                  const T* __restrict__ vel, const T* __restrict__ drho,
                  const T* __restrict__ woff, const int32_t* __restrict__ wstart,
@@ -479,7 +470,7 @@ __global__ void __launch_bounds__(kBlock)
     const T dri = drho[i];
     const T rho_i = P.rho0 + dri;
     T sum = T(0);
-    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2, uint32_t) {
         if (!(r2 > T(0))) return;
         const T r = root(r2);
         const T F = wendland_F(P, r);
@@ -492,8 +483,8 @@ __global__ void __launch_bounds__(kBlock)
         sum += F * q * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
     });
     if (nw > 0)
-        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int w, const T d[3], T r2) {
+        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                             [&](int w, const T d[3], T r2, uint32_t) {
                                  if (!(r2 > T(0))) return;
                                  const T r = root(r2);
                                  const T F = wendland_F(P, r);
@@ -518,7 +509,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_momentum(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_momentum(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                const T* __restrict__ off, const int32_t* __restrict__ fstart,
                const T* __restrict__ vel, const T* __restrict__ drho,
                const T* __restrict__ woff, const int32_t* __restrict__ wstart,
@@ -538,7 +529,7 @@ __global__ void __launch_bounds__(kBlock)
     const T p_i = P.c2 * dri;
     const T inv_rho_i = T(1) / rho_i;
     T A[3] = {0, 0, 0};
-    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2) {
+    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2, uint32_t) {
         if (!(r2 > T(0))) return;
         const T rinv = rsq(r2);
         const T r = r2 * rinv;
@@ -564,8 +555,8 @@ __global__ void __launch_bounds__(kBlock)
         for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
     });
     if (nw > 0)
-        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int w, const T d[3], T r2) {
+        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                             [&](int w, const T d[3], T r2, uint32_t) {
                                  if (!(r2 > T(0))) return;
                                  const T r = root(r2);
                                  const T F = wendland_F(P, r);
@@ -605,10 +596,75 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
+// Neighbour lists, built once per step right after the sort (the culling of
+// the 27-cell candidates happens here only; the sweeps then read dense
+// lists).  Counts keep running past the capacity so that a sweep knows to
+// fall back to the cell walk; overflows are counted in the status words.
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_lists_fluid(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+                  const T* __restrict__ off, const int32_t* __restrict__ fstart,
+                  const T* __restrict__ woff, const int32_t* __restrict__ wstart,
+                  uint32_t* __restrict__ lf, int32_t* __restrict__ cf, int capf,
+                  uint32_t* __restrict__ lw, int32_t* __restrict__ cw, int capw,
+                  uint32_t* __restrict__ status) {
+    const int64_t i = global_index();
+    if (i >= nf) return;
+    const T* o0 = off;
+    const T* o1 = off + nf;
+    const T* o2 = off + 2 * nf;
+    int c[3];
+    cell_of(P, key[i], c);
+    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
+    int n = 0;
+    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T*, T, uint32_t code) {
+        if (n < capf) lf[(int64_t)n * nf + i] = (uint32_t)j | code;
+        ++n;
+    });
+    cf[i] = n;
+    bool over = n > capf;
+    if (lw) {
+        int m = 0;
+        if (nw > 0)
+            for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                                 [&](int j, const T*, T, uint32_t code) {
+                                     if (m < capw) lw[(int64_t)m * nf + i] = (uint32_t)j | code;
+                                     ++m;
+                                 });
+        cw[i] = m;
+        over = over || m > capw;
+    }
+    if (over) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_lists_wall(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+                 const T* __restrict__ woff, const T* __restrict__ off,
+                 const int32_t* __restrict__ fstart, uint32_t* __restrict__ l,
+                 int32_t* __restrict__ cnt, int cap, uint32_t* __restrict__ status) {
+    const int64_t w = global_index();
+    if (w >= nw) return;
+    int c[3];
+    cell_of(P, wkey[w], c);
+    const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
+    int n = 0;
+    if (nf > 0)
+        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow,
+                             [&](int j, const T*, T, uint32_t code) {
+                                 if (n < cap) l[(int64_t)n * nw + w] = (uint32_t)j | code;
+                                 ++n;
+                             });
+    cnt[w] = n;
+    if (n > cap) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
+}
+
+// ---------------------------------------------------------------------------
 // FP64 diagnostics: per-block partials, then one block in fixed order.
 // ---------------------------------------------------------------------------
 
-constexpr int kDiagVals = 8;  // M, P0, P1, P2, Ek, Ep, vmax, nonfinite
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
@@ -753,13 +809,13 @@ __global__ void __launch_bounds__(kBlock)
     int cnt = 0;
     int64_t base = list ? offset[qid] : 0;
     if (nf > 0)
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi, [&](int j, const T*, T) {
+        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi, [&](int j, const T*, T, uint32_t) {
             if (list && base + cnt >= 0 && base + cnt < list_len) list[base + cnt] = pid[j];
             ++cnt;
         });
     if (which == 0 && nw > 0)
         for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int j, const T*, T) {
+                             [&](int j, const T*, T, uint32_t) {
                                  if (list && base + cnt >= 0 && base + cnt < list_len)
                                      list[base + cnt] = (int32_t)nf + wpid[j];
                                  ++cnt;
@@ -770,125 +826,6 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-
-template <typename T>
-Par<T> make_par(const sph_desc* d) {
-    Par<T> P;
-    std::memset(&P, 0, sizeof(P));
-    const double h = d->h;
-    const double alpha = d->dim == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
-    const double vol = d->dim == 2 ? d->dx * d->dx : d->dx * d->dx * d->dx;
-    P.nx = d->grid[0];
-    P.ny = d->grid[1];
-    P.nz = d->grid[2];
-    P.penalty = d->penalty_all ? 1 : 0;
-    P.L = T(d->cell);
-    P.rc2 = T(4.0 * h * h);
-    P.hinv = T(1.0 / h);
-    P.alpha = T(alpha);
-    P.gfac = T(-5.0 * alpha / (h * h));
-    P.m = T(d->rho0 * vol);
-    P.vol = T(vol);
-    P.rho0 = T(d->rho0);
-    P.c = T(d->c0);
-    P.c2 = T(d->c0 * d->c0);
-    P.cinv = T(1.0 / d->c0);
-    P.inv_c2 = T(1.0 / (d->c0 * d->c0));
-    P.mu2 = T(2.0 * d->mu);
-    P.eta2 = T(0.01 * h * h);
-    P.gamma_p = T(d->gamma_p);
-    P.two_over_dx = T(2.0 / d->dx);
-    for (int k = 0; k < 3; ++k) {
-        P.g[k] = T(d->g[k]);
-        P.gw[k] = T(d->g[k] - d->a_wall[k]);
-    }
-    P.dt = T(d->dt);
-    P.half_dt = T(0.5 * d->dt);
-    P.sigma0 = T(d->sigma0);
-    P.rho0_over_sigma0 = T(d->rho0 / d->sigma0);
-    P.psi_min = T(1e-4 / h);
-    return P;
-}
-
-GridD make_grid(const sph_desc* d) {
-    GridD G;
-    for (int k = 0; k < 3; ++k) {
-        G.lo[k] = k < d->dim ? d->lo[k] : 0.0;
-        G.n[k] = d->grid[k];
-    }
-    G.L = d->cell;
-    return G;
-}
-
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct Scratch {
-    int32_t* count;   // n_cells
-    int32_t* slot;    // max(nf, nw)
-    int32_t* perm;    // max(nf, nw)
-    int32_t* tiles;   // scan tile sums
-    int32_t* winv;    // n_wall: sorted index of each wall id (kept between calls)
-    int32_t* wkey0;   // n_wall, unsorted wall keys (init only)
-    void* woff0;      // dim * n_wall T, unsorted wall offsets (init only)
-    double* part;     // diag partials
-    size_t bytes;
-};
-
-Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
-    const size_t ts = d->precision == SPH_F64 ? 8 : 4;
-    const int64_t nmax = nf > nw ? nf : nw;
-    const int64_t ntiles = (d->n_cells + kScanTile - 1) / kScanTile + 1;
-    const int64_t ndiag = (nf + kBlock - 1) / kBlock + 1;
-    size_t o = 0;
-    Scratch s;
-    char* b = (char*)base;
-    auto take = [&](size_t bytes) {
-        char* p = b ? b + o : nullptr;
-        o += align256(bytes > 0 ? bytes : 1);
-        return (void*)p;
-    };
-    s.count = (int32_t*)take(sizeof(int32_t) * (size_t)(d->n_cells + 1));
-    s.slot = (int32_t*)take(sizeof(int32_t) * (size_t)nmax);
-    s.perm = (int32_t*)take(sizeof(int32_t) * (size_t)nmax);
-    s.tiles = (int32_t*)take(sizeof(int32_t) * (size_t)ntiles);
-    s.winv = (int32_t*)take(sizeof(int32_t) * (size_t)nw);
-    s.wkey0 = (int32_t*)take(sizeof(int32_t) * (size_t)nw);
-    s.woff0 = take(ts * (size_t)d->dim * (size_t)nw);
-    s.part = (double*)take(sizeof(double) * kDiagVals * (size_t)ndiag);
-    s.bytes = o;
-    return s;
-}
-
-#define SPH_LAUNCH_CHECK()                                 \
-    do {                                                   \
-        if (hipGetLastError() != hipSuccess) return SPH_ERR_LAUNCH; \
-    } while (0)
-
-int check_desc(const sph_desc* d) {
-    if (!d) return SPH_ERR_ARG;
-    if (d->dim != 2 && d->dim != 3) return SPH_ERR_CONFIG;
-    if (d->precision != SPH_F32 && d->precision != SPH_F64) return SPH_ERR_CONFIG;
-    if (!(d->cell > 0.0) || d->n_cells <= 0) return SPH_ERR_CONFIG;
-    return SPH_OK;
-}
-
-int check_buf(const sph_desc* d, const sph_buffers* b) {
-    if (!b) return SPH_ERR_ARG;
-    if (b->n_fluid < 0 || b->n_wall < 0) return SPH_ERR_ARG;
-    if (b->n_fluid > INT32_MAX - 1 || b->n_wall > INT32_MAX - 1) return SPH_ERR_ARG;
-    if (b->sel_vel < 0 || b->sel_vel > 1 || b->sel_rho < 0 || b->sel_rho > 1) return SPH_ERR_ARG;
-    if (!b->scratch || b->scratch_bytes < sph_scratch_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
-    if (((uintptr_t)b->scratch & 255) != 0) return SPH_ERR_ARG;
-    if (!b->status || !b->diag || !b->fstart || !b->wstart) return SPH_ERR_ARG;
-    if (b->n_fluid > 0) {
-        for (int c = 0; c < 2; ++c)
-            if (!b->key[c] || !b->pid[c] || !b->off[c] || !b->vel[c] || !b->rho[c]) return SPH_ERR_ARG;
-        if (!b->acc) return SPH_ERR_ARG;
-    }
-    if (b->n_wall > 0 && (!b->wkey || !b->wpid || !b->woff || !b->pw || !b->nrm)) return SPH_ERR_ARG;
-    if (b->n_probe < 0 || (b->n_probe > 0 && !b->probe)) return SPH_ERR_ARG;
-    return SPH_OK;
-}
 
 // Sort n keys into cell order: start table + permutation (scratch.perm).
 int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n, int32_t* start,
@@ -934,6 +871,21 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     }
     b->sel_vel = 1 - b->sel_vel;
     b->sel_rho = 1 - b->sel_rho;
+    if (b->nbr_ff) {
+        const Par<T> P = make_par<T>(d);
+        if (n > 0) {
+            hipLaunchKernelGGL((k_lists_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, b->n_wall,
+                               b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->woff, b->wstart,
+                               b->nbr_ff, b->cnt_ff, b->cap_ff, b->nbr_fw, b->cnt_fw, b->cap_fw, b->status);
+            SPH_LAUNCH_CHECK();
+        }
+        if (b->n_wall > 0) {
+            hipLaunchKernelGGL((k_lists_wall<T, D>), dim3(grid_for(b->n_wall)), dim3(kBlock), 0, st, P, n,
+                               b->n_wall, b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
+                               b->nbr_wf, b->cnt_wf, b->cap_wf, b->status);
+            SPH_LAUNCH_CHECK();
+        }
+    }
     return SPH_OK;
 }
 
@@ -942,7 +894,8 @@ int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nf == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, nw,
+    hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, list_ff(b),
+                       list_fw(b), nf, nw,
                        b->key[0], b->pid[0], (const T*)b->off[0], b->fstart, (const T*)b->woff,
                        b->wstart, (T*)b->vel[b->sel_vel], (T*)b->rho[b->sel_rho],
                        (const T*)b->acc, b->key[1], b->pid[1], (T*)b->off[1], (T*)b->sigma_out,
@@ -956,7 +909,7 @@ int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = tr
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nw == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, nf, nw,
+    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, list_wf(b), nf, nw,
                        b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
                        (const T*)b->rho[b->sel_rho], (T*)b->pw);
     SPH_LAUNCH_CHECK();
@@ -976,8 +929,8 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     const int sv = b->sel_vel, sr = b->sel_rho;
     if (which & SPH_CONTINUITY) {
         if (nf > 0) {
-            hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf,
-                               nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
+            hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
+                               list_ff(b), list_fw(b), nf, nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
                                (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
                                (const T*)b->pw, (T*)b->rho[1 - sr]);
             SPH_LAUNCH_CHECK();
@@ -986,7 +939,8 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     } else {
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
         if (nf > 0) {
-            hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, nw,
+            hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
+                               list_ff(b), list_fw(b), nf, nw,
                                b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
                                (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
                                (const T*)b->pw, (const T*)b->nrm, (T*)b->acc,

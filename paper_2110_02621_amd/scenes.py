@@ -190,23 +190,54 @@ def dam_break_3d(dx=0.004, obstacles=0, seed=0, mu=1e-3, steps=2000, headroom=0.
                  time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi, meta=meta)
 
 
-def dam_break_2d(dx=0.005, mu=1e-3, steps=1000, probe_height=0.1):
-    """2-D dam break: a 1 x 2 m column in a 4 x 3 m tank.  The probe is the
-    innermost layer of the left wall for 0 <= z <= probe_height."""
-    W, Ht = 4.0, 3.0
-    H = 2.0
-    ncol = [int(round(1.0 / dx)), int(round(H / dx))]
+def dam_break_2d(dx=0.005, mu=1e-3, steps=1000, probe_height=0.1, column_height=2.0, c0=None,
+                 gamma_p=1.0, width=1.0, tank=(4.0, 3.0)):
+    """2-D dam break: a width x column_height column in a 4 x 3 m tank.  The
+    probe is the innermost layer of the left wall for 0 < z < probe_height.
+
+    The column height is a vertical stretch of the nominal 2 m lattice
+    (z = s z_ref, s = column_height / 2; masses unchanged) with the
+    hydrostatic density of that height.  Sound speed and time step default
+    to the nominal column (c0 = 10 sqrt(2 g 2)) and do not follow a stretch
+    or a given c0: dt is held fixed."""
+    W, Ht = tank
+    H_ref = 2.0
+    ncol = [int(round(width / dx)), int(round(H_ref / dx))]
     fx = _lattice(ncol, dx)
+    s = column_height / H_ref
+    fx[:, 1] *= s
     wx = tank_walls(2, [int(round(W / dx))], int(round(Ht / dx)), dx)
     h = H_OVER_DX * dx
-    c0 = sound_speed(H)
-    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c0)
+    c_nom = sound_speed(H_ref)
+    c = c_nom if c0 is None else float(c0)
+    rho = _hydrostatic_rho(fx[:, 1], column_height, RHO_WATER, c)
     probe = np.nonzero((np.abs(wx[:, 0] + 0.5 * dx) < 1e-9 * dx + 1e-12) &
                        (wx[:, 1] > 0.0) & (wx[:, 1] < probe_height))[0]
     lo, hi = _box([-3.5 * dx, -3.5 * dx], [W + 3.5 * dx, Ht + 0.5])
-    return Scene("dam_break_2d", 2, dx, h, RHO_WATER, c0, mu, 1.0, np.array([0.0, -G, 0.0]),
-                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi,
-                 probe=probe.astype(np.int64))
+    return Scene("dam_break_2d", 2, dx, h, RHO_WATER, c, mu, gamma_p, np.array([0.0, -G, 0.0]),
+                 time_step(h, c_nom), steps, column_height, fx, np.zeros_like(fx), rho, wx, lo, hi,
+                 probe=probe.astype(np.int64), meta=dict(stretch=s, width=width, tank=tank))
+
+
+def wall_jet_2d(dx=0.01, speed=6.0, steps=120, mu=1e-3, gamma_p=1.0, probe_height=0.2):
+    """2-D block of water (0.2 x 0.2 m) launched at `speed` towards the left
+    wall of a 1 x 1 m tank, starting 1.5 dx from it: the impact drives
+    particles within dx/2 of the wall dummies, where the penalty of
+    Eqs. (13)-(15) acts.  Probe: innermost left-wall layer, z < probe_height."""
+    H = 0.2
+    n = int(round(0.2 / dx))
+    fx = _lattice([n, n], dx, shift=(1.0 * dx, 0.0))
+    fv = np.zeros_like(fx)
+    fv[:, 0] = -speed
+    wx = tank_walls(2, [int(round(1.0 / dx))], int(round(1.0 / dx)), dx)
+    h = H_OVER_DX * dx
+    c0 = sound_speed(0.3)
+    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c0)
+    probe = np.nonzero((np.abs(wx[:, 0] + 0.5 * dx) < 1e-9 * dx + 1e-12) &
+                       (wx[:, 1] > 0.0) & (wx[:, 1] < probe_height))[0]
+    lo, hi = _box([-3.5 * dx, -3.5 * dx], [1.0 + 3.5 * dx, 1.5])
+    return Scene("wall_jet_2d", 2, dx, h, RHO_WATER, c0, mu, gamma_p, np.array([0.0, -G, 0.0]),
+                 time_step(h, c0), steps, H, fx, fv, rho, wx, lo, hi, probe=probe.astype(np.int64))
 
 
 def random_box(dim=3, n=1500, seed=0, dx=0.01, box_cells=None, walls=True, H=0.3, mu=1e-3,
@@ -241,6 +272,7 @@ def by_name(name: str, **kw) -> Scene:
         "dam_break_3d": dam_break_3d,
         "dam_break_3d_obstacles": lambda **k: dam_break_3d(obstacles=8, **k),
         "dam_break_2d": dam_break_2d,
+        "wall_jet_2d": wall_jet_2d,
         "random_box": random_box,
     }
     return table[name](**kw)

@@ -44,7 +44,14 @@ def make_desc(scene, precision="f32") -> abi.Desc:
 class Solver:
     """Device-resident state of one run and the calls of the C ABI."""
 
-    def __init__(self, scene, precision="f32", device="cuda", probe=True, keep_sigma=False):
+    # Neighbour-list capacities per particle (fluid->fluid, fluid->wall,
+    # wall->fluid).  A lattice at rest has 21 (2-D) / 81 (3-D) neighbours
+    # within 2h including itself; particles beyond a capacity fall back to
+    # the cell walk (counted in the status words).
+    LIST_CAPS = {2: (40, 24, 24), 3: (128, 64, 64)}
+
+    def __init__(self, scene, precision="f32", device="cuda", probe=True, keep_sigma=False,
+                 lists=True):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = abi.load()
@@ -77,6 +84,13 @@ class Solver:
         t["status"] = torch.zeros(abi.SPH_STATUS_LEN, **i32)
         t["diag"] = torch.zeros(abi.SPH_DIAG_LEN, dtype=torch.float64, device=dev)
         t["sigma"] = torch.zeros(nf if keep_sigma else 0, dtype=T, device=dev)
+        caps = self.LIST_CAPS[dim] if lists else (0, 0, 0)
+        t["nbr_ff"] = torch.zeros((caps[0], nf), **i32)
+        t["nbr_fw"] = torch.zeros((caps[1], nf), **i32)
+        t["nbr_wf"] = torch.zeros((caps[2], nw), **i32)
+        t["cnt_ff"] = torch.zeros(nf if lists else 0, **i32)
+        t["cnt_fw"] = torch.zeros(nf if lists else 0, **i32)
+        t["cnt_wf"] = torch.zeros(nw if lists else 0, **i32)
         pr = scene.probe if (probe and len(scene.probe)) else np.zeros(0)
         t["probe"] = torch.as_tensor(np.asarray(pr, dtype=np.int32), device=dev)
 
@@ -98,6 +112,12 @@ class Solver:
         b.sigma_out = _p(t["sigma"]).value
         b.probe = _p(t["probe"]).value
         b.n_probe = int(t["probe"].numel())
+        if lists:
+            # a list array of zero size (no fluid or no walls) still needs a
+            # non-null pointer: point it at the (unused) count array
+            for name in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
+                setattr(b, name, _p(t[name]).value or _p(t["status"]).value)
+            b.cap_ff, b.cap_fw, b.cap_wf = caps
         self.buf = b
 
         def soa(a, n):
@@ -152,7 +172,8 @@ class Solver:
     def status(self):
         s = self.t["status"].cpu().numpy().astype(np.int64)
         return dict(out_of_grid=int(s[abi.SPH_STATUS_OUT_OF_GRID]), fast=int(s[abi.SPH_STATUS_FAST]),
-                    nonfinite=int(s[abi.SPH_STATUS_NONFINITE]))
+                    nonfinite=int(s[abi.SPH_STATUS_NONFINITE]),
+                    list_overflow=int(s[abi.SPH_STATUS_LIST_OVERFLOW]))
 
     def export(self):
         """Fluid state in particle-id order: pos, vel, acc (n, dim), rho (n,)."""
@@ -194,9 +215,19 @@ class Solver:
                    _p(lst), total)
         return count.cpu().numpy(), offset.cpu().numpy(), lst[:total].cpu().numpy()
 
+    def pair_counts(self):
+        """Interacting pairs of the current sorted state from the neighbour
+        list counts: fluid-fluid with self, fluid-wall, wall-fluid."""
+        t = self.t
+        if t["cnt_ff"].numel() == 0 and self.scene.n_fluid > 0:
+            raise RuntimeError("pair_counts needs the neighbour lists (Solver(..., lists=True))")
+        s = lambda x: int(x.to(torch.int64).sum().item()) if x.numel() else 0
+        return dict(ff_with_self=s(t["cnt_ff"]), fw=s(t["cnt_fw"]), wf=s(t["cnt_wf"]),
+                    max_ff=int(t["cnt_ff"].max().item()) if t["cnt_ff"].numel() else 0)
+
     def raw(self):
         """Host copies of the raw sorted buffers and the current-copy flags."""
-        out = {k: v.cpu().numpy() for k, v in self.t.items() if k not in ("scratch",)}
+        out = {k: v.cpu().numpy() for k, v in self.t.items() if k not in ("scratch", "nbr_ff", "nbr_fw", "nbr_wf")}
         out["sel_vel"] = int(self.buf.sel_vel)
         out["sel_rho"] = int(self.buf.sel_rho)
         return out

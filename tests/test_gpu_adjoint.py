@@ -1,0 +1,158 @@
+"""Hand-written adjoint against central finite differences (needs a GPU).
+
+theta = (mu, gamma_p, c0, H); J = sum_n dt mean(p_w over the probe).
+  * FP64 GPU adjoint vs FP64 GPU central differences of the same forward:
+    checks the backward kernels alone (tight bound).
+  * FP32 GPU adjoint (FP64 accumulation) vs FP64 oracle central differences
+    with a relative step of 1e-4: the end-to-end check.  The viscosity's
+    share of J is ~1e-9 of J, below what a 1e-4 step resolves in FP64, so
+    mu takes a 1e-2 step (J is linear in mu to well below that noise).
+Checkpointing (K < steps) must not change the result.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_02621_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("mu", "gamma_p", "c0", "H")
+STEP = (1e-2, 1e-4, 1e-4, 1e-4)  # relative central-difference steps
+
+
+@pytest.fixture(scope="module")
+def adj():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2110_02621_amd import adjoint
+    return adjoint
+
+
+def theta0(sc):
+    return np.array([sc.mu, sc.gamma_p, sc.c0, sc.H])
+
+
+def make(base, theta, **kw):
+    mu, gp, c0, H = theta
+    if base == "dam":
+        return scenes.dam_break_2d(mu=mu, gamma_p=gp, c0=c0, column_height=H, **kw)
+    if base == "jet":
+        sc = scenes.wall_jet_2d(mu=mu, gamma_p=gp, **kw)
+        return sc.with_params(c0=c0)
+    raise ValueError(base)
+
+
+def fd_gpu(adj, base, th, steps, prec, rel=STEP, kw=None):
+    from paper_2110_02621_amd.solver import Solver
+    kw = kw or {}
+    out = []
+    for k in range(4):
+        if base == "jet" and k == 3:
+            out.append(np.nan)
+            continue
+        h = rel[k] * abs(th[k]) if th[k] != 0 else rel[k]
+        J = []
+        for s in (+1, -1):
+            t = th.copy()
+            t[k] += s * h
+            sc = make(base, t, steps=steps, **kw)
+            S = Solver(sc, prec, probe=True)
+            S.step(steps)
+            J.append(S.diag()["J"])
+        out.append((J[0] - J[1]) / (2 * h))
+    return np.array(out)
+
+
+def fd_oracle(base, th, steps, rel=STEP, kw=None):
+    kw = kw or {}
+    out = []
+    for k in range(4):
+        if base == "jet" and k == 3:
+            out.append(np.nan)
+            continue
+        h = rel[k] * abs(th[k]) if th[k] != 0 else rel[k]
+        J = []
+        for s in (+1, -1):
+            t = th.copy()
+            t[k] += s * h
+            sc = make(base, t, steps=steps, **kw)
+            P = O.params_from_scene(sc)
+            st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe)
+            st.step(steps)
+            J.append(st.J)
+        out.append((J[0] - J[1]) / (2 * h))
+    return np.array(out)
+
+
+def compare(g, fd, th, rtol, label, zero_atol=1e-9):
+    # relative per component; a component whose differences vanish exactly
+    # (no penalty contact) must vanish in the adjoint too
+    print(f"  {label}: adjoint {g}  fd {fd}", flush=True)
+    ref = np.nanmax(np.abs(np.nan_to_num(fd) * th))
+    for k in range(4):
+        if np.isnan(fd[k]):
+            continue
+        if fd[k] == 0.0:
+            assert abs(g[k] * th[k]) <= zero_atol * ref, (NAMES[k], g[k])
+        else:
+            assert abs(g[k] - fd[k]) <= rtol * abs(fd[k]), (NAMES[k], g[k], fd[k], abs(g[k] / fd[k] - 1))
+
+
+def test_adjoint_fp64_matches_gpu_finite_differences(adj):
+    th = theta0(scenes.dam_break_2d(dx=0.04))
+    steps = 40
+    sc = make("dam", th, dx=0.04, steps=steps)
+    print(f"[adj64] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
+    r = adj.probe_gradient(sc, precision="f64", K=15)
+    g = np.array([r["grad"][n] for n in NAMES])
+    fd = fd_gpu(adj, "dam", th, steps, "f64", kw=dict(dx=0.04))
+    compare(g, fd, th, 1e-5, "dam f64")
+    # checkpoint interval does not matter
+    r2 = adj.probe_gradient(sc, precision="f64", K=steps)
+    assert np.allclose([r2["grad"][n] for n in NAMES], g, rtol=1e-12, atol=0)
+    assert r2["J"] == r["J"]
+
+
+def test_adjoint_penalty_scene_fp64(adj):
+    # a block thrown at the wall: the penalty acts, dJ/dgamma_p is not zero
+    sc0 = scenes.wall_jet_2d()
+    th = np.array([sc0.mu, sc0.gamma_p, sc0.c0, sc0.H])
+    steps = sc0.steps
+    sc = make("jet", th, steps=steps)
+    print(f"[adj-jet] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
+    r = adj.probe_gradient(sc, precision="f64", K=50)
+    g = np.array([r["grad"][n] for n in NAMES])
+    fd = fd_gpu(adj, "jet", th, steps, "f64")
+    assert abs(fd[1]) > 0.0
+    compare(g, fd, th, 1e-4, "jet f64")
+
+
+def test_adjoint_fp32_matches_oracle_finite_differences(adj):
+    # FP32 forward, FP64 gradient accumulation, against FP64 central
+    # differences of the oracle with a relative step of 1e-4.
+    kw = dict(dx=0.02)
+    th = theta0(scenes.dam_break_2d(**kw))
+    steps = 100
+    sc = make("dam", th, steps=steps, **kw)
+    print(f"[adj32] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
+    r = adj.probe_gradient(sc, precision="f32", K=25)
+    g = np.array([r["grad"][n] for n in NAMES])
+    fd = fd_oracle("dam", th, steps, kw=kw)
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe).step(steps)
+    print(f"  J gpu {r['J']:.9e} oracle {st.J:.9e}", flush=True)
+    assert abs(r["J"] - st.J) <= 1e-4 * abs(st.J)
+    compare(g, fd, th, 1e-3, "dam f32 vs oracle")
+
+
+def test_autograd_function(adj):
+    import torch
+    th = torch.tensor(theta0(scenes.dam_break_2d(dx=0.04)), dtype=torch.float64, requires_grad=True)
+    J = adj.ProbeFunctional.apply(th, "f64", 10, dict(dx=0.04, steps=20))
+    J.backward()
+    assert th.grad is not None and torch.isfinite(th.grad).all()
+    sc = make("dam", th.detach().numpy(), dx=0.04, steps=20)
+    r = adj.probe_gradient(sc, precision="f64", K=10)
+    assert np.allclose(th.grad.numpy(), [r["grad"][n] for n in NAMES], rtol=1e-12)

@@ -186,7 +186,7 @@ def test_trajectory_steps_1_10_100(solver_mod, name, prec):
     od = st.diag()
     assert d["M"] == pytest.approx(od["M"], rel=1e-12)
     assert d["steps"] == 100
-    assert S.status() == dict(out_of_grid=0, fast=0, nonfinite=0)
+    assert S.status() == dict(out_of_grid=0, fast=0, nonfinite=0, list_overflow=0)
 
 
 def test_hydrostatic_tank_fp64(solver_mod):
@@ -305,3 +305,91 @@ def test_edge_coincident_particles(solver_mod):
     S.step(2)
     e = S.export()
     assert np.all(np.isfinite(e["acc"])) and np.all(np.isfinite(e["rho"]))
+
+
+# ---------------------------------------------------------------- full size, sampled
+FULL = {
+    "dam3d_dx0.004": lambda: scenes.dam_break_3d(dx=0.004),
+    "dam3d_obst_dx0.0025": lambda: scenes.dam_break_3d(dx=0.0025, obstacles=8, seed=0),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_sampled_parity(solver_mod, name):
+    # The workloads at full size in the launch configuration the bench
+    # times (FP32, sph_step), two steps in; then one step stage by stage,
+    # compared on sampled particles that the oracle evaluates one by one.
+    sc = FULL[name]()
+    print(f"[full] {name} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
+    s = scales(sc)
+    S = solver_mod.Solver(sc, "f32")
+    S.step(2)
+    P = O.params_from_scene(sc)
+    rng = np.random.default_rng(5)
+    e0, w0 = S.export(), S.export_walls()
+    wx, wn = w0["pos"], w0["nrm"]
+    near_wall = np.nonzero(e0["pos"][:, 2] < 3 * sc.dx)[0]
+    qf = np.unique(np.concatenate([rng.choice(sc.n_fluid, 3000, replace=False),
+                                   rng.choice(near_wall, 1000, replace=False)]))
+    qw = rng.choice(sc.n_wall, 2000, replace=False)
+    # neighbour sets of the sampled particles: equal to the FP64 cell-list
+    # sets except for pairs within a few ulps of the cut-off
+    cnt, off, lst = S.neighbours(0)
+    allx = np.concatenate([e0["pos"], wx])
+    ocnt, olst = O.neighbours(3, sc.h, e0["pos"][qf], allx)
+    oo = np.concatenate([[0], np.cumsum(ocnt)])
+    nborder = 0
+    for a, i in enumerate(qf):
+        g = set(lst[off[i]:off[i] + cnt[i]].tolist())
+        o = set(olst[oo[a]:oo[a + 1]].tolist())
+        for j in g ^ o:
+            r = np.linalg.norm(allx[j] - e0["pos"][i])
+            assert abs(r - 2 * sc.h) < 1e-6 * sc.h, (i, j, r)
+            nborder += 1
+    print(f"  pairs at the cut-off (within 1e-6 h): {nborder}", flush=True)
+    # density stage
+    S.density()
+    e_mid = S.export()   # rho: reinitialised, vel: half step (positions still r^n in copy 0)
+    sig_o = O.sigma(P, e0["pos"], wx, query=qf)
+    rt_o = O.reinit(P, sig_o, e0["rho"][qf])
+    errs = dict(p_reinit=scaled(sc.c0 ** 2 * (e_mid["rho"][qf] - rt_o), 0, s["p"]),
+                v_half=scaled(e_mid["vel"][qf], e0["vel"][qf] + 0.5 * sc.dt * e0["acc"][qf], s["v"]))
+    S.build_cells()
+    e1 = S.export()
+    errs["x1"] = scaled(e1["pos"][qf], e0["pos"][qf] + sc.dt * e1["vel"][qf], s["x"])
+    S.wall_bc()
+    pw1 = S.export_walls()["pw"]
+    errs["pw"] = scaled(pw1[qw], O.wall_pressure(P, wx, e1["pos"], e1["rho"], query=qw), s["p"])
+    S.continuity()
+    e2 = S.export()
+    D_o = O.continuity(P, e1["pos"], e1["vel"], e1["rho"], wx, pw1, query=qf)
+    errs["p_new"] = scaled(sc.c0 ** 2 * (e2["rho"][qf] - (e1["rho"][qf] + sc.dt * D_o)), 0, s["p"])
+    S.momentum()
+    e3 = S.export()
+    A_o = O.momentum(P, e1["pos"], e1["vel"], e2["rho"], wx, pw1, wn, query=qf)
+    errs["acc"] = scaled(e3["acc"][qf], A_o, max(G, np.abs(A_o).max()))
+    errs["v_new"] = scaled(e3["vel"][qf], e1["vel"][qf] + 0.5 * sc.dt * A_o, s["v"])
+    print("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), S.status(), flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= TOL32}
+    assert not bad, bad
+    assert S.status() == dict(out_of_grid=0, fast=0, nonfinite=0, list_overflow=0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["box3d", "dam3d", "dam2d"])
+def test_lists_and_cell_walk_agree_bitwise(solver_mod, name, prec):
+    # The sweeps read neighbour lists when present and walk the cells
+    # otherwise: same pairs, same order, same arithmetic, same bits.
+    sc = SMALL[name]()
+    a = solver_mod.Solver(sc, prec, lists=True)
+    b = solver_mod.Solver(sc, prec, lists=False)
+    a.step(10)
+    b.step(10)
+    ea, eb = a.export(), b.export()
+    for k in ("pos", "vel", "rho", "acc"):
+        assert np.array_equal(ea[k], eb[k]), k
+    assert np.array_equal(a.export_walls()["pw"], b.export_walls()["pw"])
+    st = a.status()
+    assert st["list_overflow"] == 0
+    raw = a.raw()
+    assert raw["cnt_ff"].max() <= solver_mod.Solver.LIST_CAPS[sc.dim][0]
