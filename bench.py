@@ -60,6 +60,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--adj-steps", type=int, default=1000, help="steps of the differentiable 2-D dam break")
+    ap.add_argument("--adj-dx", type=float, default=0.005)
+    ap.add_argument("--adj-K", type=int, default=50, help="checkpoint interval of the adjoint")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also run one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -155,6 +161,30 @@ def main():
         del S64
         torch.cuda.empty_cache()
 
+    adj = None
+    if not args.no_adjoint:
+        from paper_2110_02621_amd import adjoint
+        sc4 = scenes.dam_break_2d(dx=args.adj_dx, steps=args.adj_steps)
+        adjoint.probe_gradient(scenes.dam_break_2d(dx=args.adj_dx, steps=2 * args.adj_K),
+                               precision="f32", K=args.adj_K)  # warm-up (kernels, allocator)
+        r = adjoint.probe_gradient(sc4, precision="f32", K=args.adj_K, return_timings=True)
+        adj = dict(workload=f"2-D dam break dx={args.adj_dx} m ({sc4.n_fluid} fluid + {sc4.n_wall} wall), "
+                            f"{args.adj_steps} steps, checkpoint every {args.adj_K}",
+                   t_forward_s=r["t_forward"], t_backward_s=r["t_backward"],
+                   ratio=r["t_backward"] / r["t_forward"], J=r["J"], grad=r["grad"])
+        print(f"[bench] adjoint fwd {r['t_forward']:.3f} s bwd {r['t_backward']:.3f} s grad {r['grad']}",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * 2 ** 30 // 4)
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -191,7 +221,8 @@ def main():
         "fluid_particle_steps_per_s": nf * args.steps / wall,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
-        "adjoint_fwd_ratio": None,
+        "adjoint_fwd_ratio": adj["ratio"] if adj else None,
+        "adjoint": adj,
         "roofline": roofline,
         "roofline_frac_unpacked_fp32": round(ach / PEAK_FP32_UNPACKED, 4),
         "kernels": kernels,

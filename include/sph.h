@@ -60,8 +60,8 @@ extern "C" {
 #define SPH_STATUS_OUT_OF_GRID 0 /* particle steps whose drift left the cell grid (clamped) */
 #define SPH_STATUS_FAST 1        /* drifts longer than one cell per step (CFL violated) */
 #define SPH_STATUS_NONFINITE 2   /* non-finite values met by sph_diag */
-#define SPH_STATUS_LIST_OVERFLOW 3 /* particles with more neighbours than a list holds (those
-                                      sweep the cells instead: slower, same result) */
+#define SPH_STATUS_LIST_OVERFLOW 3 /* queries with a stencil row of more than 128 candidates
+                                      (those walk the cells instead: slower, same result) */
 #define SPH_STATUS_LEN 4
 
 /* Diagnostics written by sph_diag (double[SPH_DIAG_LEN], device). */
@@ -134,18 +134,19 @@ typedef struct sph_buffers {
     const int32_t *probe;  /* optional: wall ids of the probe patch (device) */
     int32_t n_probe;
     int32_t reserved;
-    /* Optional neighbour lists (all three or none).  When given,
+    /* Optional neighbour masks (all three or none).  When given,
      * sph_build_cells fills them for the sorted state and every sweep reads
-     * them instead of walking the cells (same pairs, same order, same
-     * arithmetic).  Entry k of query q is list[k * n_query + q]: the sorted
-     * index of the neighbour in the low 26 bits, the cell shift + 1 per axis
-     * in two bits each above (n_fluid, n_wall < 2^26).  count[q] holds the
-     * full neighbour count, which may exceed cap. */
-    uint32_t *nbr_ff;  /* fluid -> fluid, uint32[cap_ff][n_fluid] */
-    uint32_t *nbr_fw;  /* fluid -> wall, uint32[cap_fw][n_fluid] */
-    uint32_t *nbr_wf;  /* wall -> fluid, uint32[cap_wf][n_wall] */
+     * them instead of testing all stencil candidates (same pairs, same
+     * order, same arithmetic).  For query q and stencil row r (the rows of
+     * three x-adjacent cells around q's cell, r = (dz+1)*3 + (dy+1) in 3-D,
+     * dy+1 in 2-D) the words mask[(2*r + w) * n_query + q], w = 0, 1, have
+     * bit b set when candidate base_r + 64*w + b of the row's index range is
+     * a neighbour.  count[q] is the number of neighbours, or -1 when a row
+     * had more than 128 candidates (that query then walks the cells). */
+    uint64_t *nbr_ff;  /* fluid -> fluid, uint64[rows][2][n_fluid] */
+    uint64_t *nbr_fw;  /* fluid -> wall, uint64[rows][2][n_fluid] */
+    uint64_t *nbr_wf;  /* wall -> fluid, uint64[rows][2][n_wall] */
     int32_t *cnt_ff, *cnt_fw, *cnt_wf;
-    int32_t cap_ff, cap_fw, cap_wf, reserved3;
 } sph_buffers;
 
 /* Validates the run description and fills its derived fields: L_c = 2h
@@ -153,8 +154,9 @@ typedef struct sph_buffers {
  * density sum_j W of a full square/cubic lattice of spacing dx (the initial
  * reference value of Eq. (17)).  Host only.  SPH_ERR_CONFIG for dim not in
  * {2, 3}, unknown precision, h <= 0, dx <= 0, c0 <= 0, hi <= lo, more than
- * 2^31 - 2 cells, or dt above min(0.25 h/(1.1 c0), 0.25 sqrt(h/|g|))
- * (Eqs. (23)-(24) with the anticipated maximum velocity c0/10). */
+ * 2^31 - 2 cells, or dt more than 1 % above min(0.25 h/(1.1 c0),
+ * 0.25 sqrt(h/|g|)) (Eqs. (23)-(24) with the anticipated maximum velocity
+ * c0/10; the slack lets c0 be varied at a fixed dt). */
 int sph_configure(sph_desc *desc);
 
 /* Bytes of scratch the calls need for n_fluid fluid and n_wall wall
@@ -179,7 +181,7 @@ int sph_init(const sph_desc *desc, sph_buffers *buf, const double *fpos, const d
  * Stable counting sort of the drifted fluid (key[1], off[1], pid[1] and the
  * current velocity and density) by cell key into key[0], off[0], pid[0] and
  * the other velocity/density copy; particles of one cell keep their prior
- * order.  Rebuilds fstart and, if present, the neighbour lists.  Swaps
+ * order.  Rebuilds fstart and, if present, the neighbour masks.  Swaps
  * sel_vel and sel_rho. */
 int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
 

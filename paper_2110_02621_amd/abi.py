@@ -52,7 +52,6 @@ class Buffers(C.Structure):
         ("probe", C.c_void_p), ("n_probe", C.c_int32), ("reserved", C.c_int32),
         ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
         ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p),
-        ("cap_ff", C.c_int32), ("cap_fw", C.c_int32), ("cap_wf", C.c_int32), ("reserved3", C.c_int32),
     ]
 
 

@@ -1,6 +1,7 @@
 // sph_device.h -- device-side building blocks of the gfx950 SPH hot path:
 // run constants, XCD-aware block numbering, the cell+offset pair distance,
-// the 27-cell (3-D) / 9-cell (2-D) neighbour walk and the Wendland kernel.
+// the 27-cell (3-D) / 9-cell (2-D) neighbour walk, neighbour bitmasks and
+// the Wendland kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -95,13 +96,74 @@ __device__ __forceinline__ void cell_of(const Par<T>& P, int key, int c[3]) {
     c[2] = t / P.ny;
 }
 
-// Neighbour list entries: index j in the low 26 bits, the cell shift
-// c_j - c_i + 1 per axis in two bits each above it.
+// Cell shift code of a pair: c_j - c_i + 1 per axis in two bits each,
+// above bit 26 (passed to the neighbour callbacks).
 constexpr uint32_t kIdxBits = 26;
-constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
 
 __device__ __forceinline__ uint32_t shift_code(int sx, int sy, int sz) {
     return (uint32_t)((sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4)) << kIdxBits;
+}
+
+// The neighbour stencil is the 3 (2-D) or 9 (3-D) (y, z) rows of three
+// x-adjacent cells around the query's cell, numbered (dz + 1) * 3 + (dy + 1).
+// A row is skipped when its y/z gap alone puts all of it beyond the support,
+// its left or right cell when the x gap does.  The margin (1 + 1e-5) on rc2
+// keeps every skip conservative against rounding, so the pair set (decided
+// by the exact r^2 < rc2 test) is unchanged.
+constexpr int kMaskWords = 2;  // 128 candidates per row
+constexpr double kSkipMargin = 1.0 + 1e-5;
+
+template <typename T>
+__device__ __forceinline__ T gap(int dcell, T o, T L) {
+    return dcell < 0 ? o : (dcell > 0 ? L - o : T(0));
+}
+
+template <int D>
+__device__ __forceinline__ int stencil_row(int dy, int dz) {
+    return D == 3 ? (dz + 1) * 3 + (dy + 1) : (dy + 1);
+}
+
+// One stencil row as the walk, the mask builder and the mask sweep all see
+// it: cell starts and the (possibly trimmed) candidate range.
+struct Row {
+    int base;    // start of the row's full 3-cell range (mask bit 0)
+    int jm, jp;  // start and end of the query's own cell in the row
+    int j0, j1;  // candidate range after trimming
+    int r;       // stencil row number
+    uint32_t cyz;
+};
+
+// Iterate the rows of query (c, oi); g(row, sy, sz) is called per row kept.
+template <typename T, int D, typename G>
+__device__ __forceinline__ void for_rows(const Par<T>& P, const int32_t* __restrict__ start,
+                                         const int c[3], const T oi[3], G&& g) {
+    const T reach = P.rc2 * T(kSkipMargin);
+    const int zlo = D == 3 ? max(c[2] - 1, 0) : 0;
+    const int zhi = D == 3 ? min(c[2] + 1, P.nz - 1) : 0;
+    const int ylo = max(c[1] - 1, 0), yhi = min(c[1] + 1, P.ny - 1);
+    const T gl = oi[0], gr = P.L - oi[0];
+    for (int z = zlo; z <= zhi; ++z) {
+        const T sz = T(z - c[2]) * P.L;
+        const T gz = D == 3 ? gap(z - c[2], oi[2], P.L) : T(0);
+        for (int y = ylo; y <= yhi; ++y) {
+            const T gy = gap(y - c[1], oi[1], P.L);
+            const T g2 = gy * gy + gz * gz;
+            if (!(g2 < reach)) continue;
+            const T rx2 = reach - g2;
+            const int row = P.nx * (y + P.ny * z);
+            const bool left = c[0] > 0 && gl * gl < rx2;
+            const bool right = c[0] < P.nx - 1 && gr * gr < rx2;
+            Row R;
+            R.base = start[row + max(c[0] - 1, 0)];
+            R.jm = start[row + c[0]];
+            R.jp = start[row + c[0] + 1];
+            R.j0 = left ? R.base : R.jm;
+            R.j1 = right ? start[row + c[0] + 2] : R.jp;
+            R.r = stencil_row<D>(y - c[1], z - c[2]);
+            R.cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
+            g(R, T(y - c[1]) * P.L, sz);
+        }
+    }
 }
 
 // Visit every particle j of a cell-sorted set with |r_i - r_j|^2 < rc2,
@@ -109,78 +171,100 @@ __device__ __forceinline__ uint32_t shift_code(int sx, int sy, int sz) {
 // are adjacent in key order, so each (y, z) row of 3 cells is one
 // contiguous index range; the cell of j inside the row follows from the
 // row's cell starts.  f(j, d, r2, code) receives d = r_i - r_j and the
-// shift code of the pair.
+// shift code of the pair.  Pairs come row by row in ascending j.
 template <typename T, int D, typename F>
 __device__ __forceinline__ void for_neighbours(const Par<T>& P, const int32_t* __restrict__ start,
                                                const T* __restrict__ o0, const T* __restrict__ o1,
                                                const T* __restrict__ o2, const int c[3],
                                                const T oi[3], F&& f) {
-    const int zlo = D == 3 ? max(c[2] - 1, 0) : 0;
-    const int zhi = D == 3 ? min(c[2] + 1, P.nz - 1) : 0;
-    const int ylo = max(c[1] - 1, 0), yhi = min(c[1] + 1, P.ny - 1);
-    const int xlo = max(c[0] - 1, 0), xhi = min(c[0] + 1, P.nx - 1);
-    for (int z = zlo; z <= zhi; ++z) {
-        const T sz = T(z - c[2]) * P.L;
-        for (int y = ylo; y <= yhi; ++y) {
-            const T sy = T(y - c[1]) * P.L;
-            const uint32_t cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
-            const int row = P.nx * (y + P.ny * z);
-            const int j0 = start[row + xlo];
-            const int jm = start[row + c[0]];
-            const int jp = start[row + c[0] + 1];
-            const int j1 = start[row + xhi + 1];
-            for (int j = j0; j < j1; ++j) {
-                const int ix = j < jm ? -1 : (j < jp ? 0 : 1);
-                const T sx = T(ix) * P.L;
-                T d[3];
-                const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), sx, sy, sz, d);
-                if (r2 < P.rc2) f(j, d, r2, cyz | ((uint32_t)(ix + 1) << kIdxBits));
-            }
+    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
+        for (int j = R.j0; j < R.j1; ++j) {
+            const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+            T d[3];
+            const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
+            if (r2 < P.rc2) f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits));
         }
-    }
+    });
 }
 
-// Neighbour list of one query particle: entry k at list[k * stride + i]
-// (interleaved: a wave reads one entry of 64 particles in one coalesced
-// access).  The distance is recomputed exactly as in the cell walk, so a
-// sweep over the list sees bit-identical d and r^2, in the same order.
-struct NbrList {
-    const uint32_t* list;  // null: no list, walk the cells
+// Neighbour masks of one set: for query q and stencil row r, the words
+// mask[(r * kMaskWords + w) * n + q] hold one bit per candidate of the
+// row's full 3-cell index range: bit b of word w marks candidate
+// base + 64 w + b as a pair.  count[q] is the number of pairs, or -1 when a
+// row had more than 128 candidates (that query walks the cells instead).
+// Storage is interleaved across queries: a wave reads or writes one word
+// of 64 queries in one coalesced access.
+struct NbrMask {
+    const uint64_t* mask;  // null: no masks, walk the cells
     const int32_t* count;
-    int64_t stride;
-    int cap;
+    int64_t n;
 };
 
-template <typename T, int D, typename F>
-__device__ __forceinline__ void for_list(const Par<T>& P, const uint32_t* __restrict__ list,
-                                         int64_t stride, int64_t i, int n,
-                                         const T* __restrict__ o0, const T* __restrict__ o1,
-                                         const T* __restrict__ o2, const T oi[3], F&& f) {
-    for (int k = 0; k < n; ++k) {
-        const uint32_t e = list[(int64_t)k * stride + i];
-        const int j = (int)(e & kIdxMask);
-        const T sx = T((int)((e >> 26) & 3u) - 1) * P.L;
-        const T sy = T((int)((e >> 28) & 3u) - 1) * P.L;
-        const T sz = T((int)((e >> 30) & 3u) - 1) * P.L;
-        T d[3];
-        const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), sx, sy, sz, d);
-        f(j, d, r2, e & ~kIdxMask);
-    }
+// Build the masks of query i (rows kept by the walk only).  Returns the
+// pair count, or -1 on a row with more than 128 candidates.
+template <typename T, int D>
+__device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __restrict__ start,
+                                          const T* __restrict__ o0, const T* __restrict__ o1,
+                                          const T* __restrict__ o2, const int c[3], const T oi[3],
+                                          uint64_t* __restrict__ mask, int64_t n, int64_t i) {
+    int count = 0;
+    bool over = false;
+    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
+        uint64_t m0 = 0, m1 = 0;
+        if (R.j1 - R.base > 64 * kMaskWords) over = true;
+        for (int j = R.j0; j < R.j1; ++j) {
+            const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+            T d[3];
+            const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
+            if (r2 < P.rc2) {
+                const int b = j - R.base;
+                if (b < 64) m0 |= 1ull << b;
+                else if (b < 128) m1 |= 1ull << (b - 64);
+                ++count;
+            }
+        }
+        mask[(int64_t)(R.r * kMaskWords + 0) * n + i] = m0;
+        mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
+    });
+    return over ? -1 : count;
 }
 
-// The neighbours of query i: from its list when one exists and did not
+// Visit the pairs recorded in the masks of query i: same rows and the
+// same ascending order as the walk, so sums are bit-identical to it.
+template <typename T, int D, typename F>
+__device__ __forceinline__ void for_mask(const Par<T>& P, const int32_t* __restrict__ start,
+                                         const T* __restrict__ o0, const T* __restrict__ o1,
+                                         const T* __restrict__ o2, const int c[3], const T oi[3],
+                                         const uint64_t* __restrict__ mask, int64_t n, int64_t i,
+                                         F&& f) {
+    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
+        const uint64_t m[kMaskWords] = {mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
+                                        mask[(int64_t)(R.r * kMaskWords + 1) * n + i]};
+#pragma unroll
+        for (int w = 0; w < kMaskWords; ++w) {
+            uint64_t bits = m[w];
+            while (bits) {
+                const int j = R.base + 64 * w + __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+                T d[3];
+                const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
+                f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits));
+            }
+        }
+    });
+}
+
+// The neighbours of query i: from its masks when they exist and did not
 // overflow, else by walking the cells.
 template <typename T, int D, typename F>
-__device__ __forceinline__ void visit(const Par<T>& P, const NbrList& NL, int64_t i,
+__device__ __forceinline__ void visit(const Par<T>& P, const NbrMask& M, int64_t i,
                                       const int32_t* __restrict__ start, const T* __restrict__ o0,
                                       const T* __restrict__ o1, const T* __restrict__ o2,
                                       const int c[3], const T oi[3], F&& f) {
-    if (NL.list) {
-        const int n = NL.count[i];
-        if (n <= NL.cap) {
-            for_list<T, D>(P, NL.list, NL.stride, i, n, o0, o1, o2, oi, f);
-            return;
-        }
+    if (M.mask && M.count[i] >= 0) {
+        for_mask<T, D>(P, start, o0, o1, o2, c, oi, M.mask, M.n, i, f);
+        return;
     }
     for_neighbours<T, D>(P, start, o0, o1, o2, c, oi, f);
 }

@@ -77,15 +77,16 @@ inline GridD make_grid(const sph_desc* d) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Lists of the current sorted state (see sph_buffers); {null} when absent.
-inline NbrList list_ff(const sph_buffers* b) {
-    return b->nbr_ff ? NbrList{b->nbr_ff, b->cnt_ff, b->n_fluid, b->cap_ff} : NbrList{nullptr, nullptr, 0, 0};
+// Neighbour masks of the current sorted state (see sph_buffers); {null}
+// when absent.
+inline NbrMask mask_ff(const sph_buffers* b) {
+    return b->nbr_ff ? NbrMask{b->nbr_ff, b->cnt_ff, b->n_fluid} : NbrMask{nullptr, nullptr, 0};
 }
-inline NbrList list_fw(const sph_buffers* b) {
-    return b->nbr_fw ? NbrList{b->nbr_fw, b->cnt_fw, b->n_fluid, b->cap_fw} : NbrList{nullptr, nullptr, 0, 0};
+inline NbrMask mask_fw(const sph_buffers* b) {
+    return b->nbr_fw ? NbrMask{b->nbr_fw, b->cnt_fw, b->n_fluid} : NbrMask{nullptr, nullptr, 0};
 }
-inline NbrList list_wf(const sph_buffers* b) {
-    return b->nbr_wf ? NbrList{b->nbr_wf, b->cnt_wf, b->n_wall, b->cap_wf} : NbrList{nullptr, nullptr, 0, 0};
+inline NbrMask mask_wf(const sph_buffers* b) {
+    return b->nbr_wf ? NbrMask{b->nbr_wf, b->cnt_wf, b->n_wall} : NbrMask{nullptr, nullptr, 0};
 }
 
 struct Scratch {
@@ -153,11 +154,9 @@ inline int check_buf(const sph_desc* d, const sph_buffers* b) {
     }
     if (b->n_wall > 0 && (!b->wkey || !b->wpid || !b->woff || !b->pw || !b->nrm)) return SPH_ERR_ARG;
     if (b->n_probe < 0 || (b->n_probe > 0 && !b->probe)) return SPH_ERR_ARG;
-    const bool lists = b->nbr_ff || b->nbr_fw || b->nbr_wf;
-    if (lists) {  // all three or none, indices must fit the entry's 26 bits
+    const bool masks = b->nbr_ff || b->nbr_fw || b->nbr_wf;
+    if (masks) {  // all three or none
         if (!b->nbr_ff || !b->nbr_fw || !b->nbr_wf || !b->cnt_ff || !b->cnt_fw || !b->cnt_wf) return SPH_ERR_ARG;
-        if (b->cap_ff < 1 || b->cap_fw < 1 || b->cap_wf < 1) return SPH_ERR_ARG;
-        if (b->n_fluid > (int64_t)kIdxMask || b->n_wall > (int64_t)kIdxMask) return SPH_ERR_ARG;
     }
     return SPH_OK;
 }

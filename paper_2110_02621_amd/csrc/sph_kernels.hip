@@ -60,11 +60,32 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 //   5. gather of every field through perm.
 // ---------------------------------------------------------------------------
 
+// The keys arrive nearly sorted (the previous order, drifted by less than
+// a cell), so runs of equal keys are common inside a wave: each run's first
+// lane adds the run length with one atomic and the run takes consecutive
+// slots after the returned base.
 __global__ void __launch_bounds__(kBlock) k_hist(const int32_t* __restrict__ key, int64_t n,
                                                   int32_t* __restrict__ count,
                                                   int32_t* __restrict__ slot) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) slot[i] = atomicAdd(&count[key[i]], 1);
+    const bool valid = i < n;
+    const int k = valid ? key[i] : -1;
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(k, 1, 64);
+    const bool head = valid && (lane == 0 || prev != k);
+    const uint64_t heads = __ballot(head);
+    const uint64_t vmask = __ballot(valid);
+    // this lane's run: from the last head at or below it to the next head
+    const uint64_t below = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
+    const int first = 63 - __builtin_clzll(below | 1ull);
+    const uint64_t above = heads & ~((2ull << lane) - 1) & ((lane == 63) ? 0ull : ~0ull);
+    const int next = above ? __builtin_ctzll(above) : 64;
+    const int vend = 64 - __builtin_clzll(vmask | 1ull);  // one past the last valid lane
+    const int len = min(next, vend) - first;
+    int base = 0;
+    if (head) base = atomicAdd(&count[k], len);
+    base = __shfl(base, first, 64);
+    if (valid) slot[i] = base + (lane - first);
 }
 
 
@@ -339,7 +360,7 @@ __device__ __forceinline__ int renormalise(T& o, T L, uint32_t* status) {
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_density(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_density(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
               const int32_t* __restrict__ pid, const T* __restrict__ off,
               const int32_t* __restrict__ fstart, const T* __restrict__ woff,
               const int32_t* __restrict__ wstart, T* __restrict__ vel, T* __restrict__ drho,
@@ -397,7 +418,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_wall_bc(Par<T> P, NbrList LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+    k_wall_bc(Par<T> P, NbrMask LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
               const T* __restrict__ woff, const T* __restrict__ off,
               const int32_t* __restrict__ fstart, const T* __restrict__ drho, T* __restrict__ pw) {
     const int64_t w = global_index();
@@ -453,7 +474,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_continuity(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_continuity(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                  const T* __restrict__ off, const int32_t* __restrict__ fstart,
                  const T* __restrict__ vel, const T* __restrict__ drho,
                  const T* __restrict__ woff, const int32_t* __restrict__ wstart,
@@ -509,7 +530,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_momentum(Par<T> P, NbrList LF, NbrList LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_momentum(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                const T* __restrict__ off, const int32_t* __restrict__ fstart,
                const T* __restrict__ vel, const T* __restrict__ drho,
                const T* __restrict__ woff, const int32_t* __restrict__ wstart,
@@ -596,86 +617,70 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour lists, built once per step right after the sort (the culling of
-// the 27-cell candidates happens here only; the sweeps then read dense
-// lists).  Counts keep running past the capacity so that a sweep knows to
-// fall back to the cell walk; overflows are counted in the status words.
+// Neighbour masks, built once per step right after the sort: the culling of
+// the stencil candidates happens here only, and every row's result is one
+// coalesced store of two 64-bit words; the sweeps then visit the recorded
+// pairs.  Queries with a row of more than 128 candidates get count -1 and
+// walk the cells in the sweeps (counted in the status words).
 // ---------------------------------------------------------------------------
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_lists_fluid(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_masks_fluid(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                   const T* __restrict__ off, const int32_t* __restrict__ fstart,
                   const T* __restrict__ woff, const int32_t* __restrict__ wstart,
-                  uint32_t* __restrict__ lf, int32_t* __restrict__ cf, int capf,
-                  uint32_t* __restrict__ lw, int32_t* __restrict__ cw, int capw,
-                  uint32_t* __restrict__ status) {
+                  uint64_t* __restrict__ mf, int32_t* __restrict__ cf, uint64_t* __restrict__ mw,
+                  int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
     const int64_t i = global_index();
     if (i >= nf) return;
-    const T* o0 = off;
-    const T* o1 = off + nf;
-    const T* o2 = off + 2 * nf;
     int c[3];
     cell_of(P, key[i], c);
-    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
-    int n = 0;
-    for_neighbours<T, D>(P, fstart, o0, o1, o2, c, oi, [&](int j, const T*, T, uint32_t code) {
-        if (n < capf) lf[(int64_t)n * nf + i] = (uint32_t)j | code;
-        ++n;
-    });
+    const T oi[3] = {off[i], off[nf + i], D == 3 ? off[2 * nf + i] : T(0)};
+    const int n = build_mask<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi, mf, nf, i);
     cf[i] = n;
-    bool over = n > capf;
-    if (lw) {
-        int m = 0;
-        if (nw > 0)
-            for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                                 [&](int j, const T*, T, uint32_t code) {
-                                     if (m < capw) lw[(int64_t)m * nf + i] = (uint32_t)j | code;
-                                     ++m;
-                                 });
-        cw[i] = m;
-        over = over || m > capw;
-    }
-    if (over) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
+    int m = 0;
+    if (nw > 0) m = build_mask<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi, mw, nf, i);
+    cw[i] = m;
+    if (n < 0 || m < 0) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_lists_wall(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+    k_masks_wall(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
                  const T* __restrict__ woff, const T* __restrict__ off,
-                 const int32_t* __restrict__ fstart, uint32_t* __restrict__ l,
-                 int32_t* __restrict__ cnt, int cap, uint32_t* __restrict__ status) {
+                 const int32_t* __restrict__ fstart, uint64_t* __restrict__ m,
+                 int32_t* __restrict__ cnt, uint32_t* __restrict__ status) {
     const int64_t w = global_index();
     if (w >= nw) return;
     int c[3];
     cell_of(P, wkey[w], c);
     const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
     int n = 0;
-    if (nf > 0)
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow,
-                             [&](int j, const T*, T, uint32_t code) {
-                                 if (n < cap) l[(int64_t)n * nw + w] = (uint32_t)j | code;
-                                 ++n;
-                             });
+    if (nf > 0) n = build_mask<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow, m, nw, w);
     cnt[w] = n;
-    if (n > cap) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
+    if (n < 0) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 diagnostics: per-block partials, then one block in fixed order.
 // ---------------------------------------------------------------------------
 
+// Exact FP64 particle mass and body force of the reductions (by value).
+struct DiagC {
+    double m;
+    double g[3];
+};
+
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_diag_partial(Par<T> P, GridD G, int64_t nf, const int32_t* __restrict__ key,
-                   const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ drho,
-                   double* __restrict__ part) {
+    k_diag_partial(Par<T> P, GridD G, DiagC K, int64_t nf,
+                   const int32_t* __restrict__ key, const T* __restrict__ off,
+                   const T* __restrict__ vel, const T* __restrict__ drho, double* __restrict__ part) {
     __shared__ double red[kDiagVals][kBlock];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < nf) {
-        const double m = (double)P.m;
         int c[3];
         cell_of(P, key[i], c);
         double v2 = 0.0, gx = 0.0;
@@ -684,13 +689,13 @@ __global__ void __launch_bounds__(kBlock)
             const double vk = (double)vel[k * nf + i];
             const double xk = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
             finite = finite && isfinite(vk) && isfinite(xk);
-            v[1 + k] = m * vk;
+            v[1 + k] = K.m * vk;
             v2 += vk * vk;
-            gx += (double)P.g[k] * xk;
+            gx += K.g[k] * xk;
         }
-        v[0] = m;
-        v[4] = 0.5 * m * v2;
-        v[5] = -m * gx;
+        v[0] = K.m;
+        v[4] = 0.5 * K.m * v2;
+        v[5] = -K.m * gx;
         v[6] = sqrt(v2);
         v[7] = finite ? 0.0 : 1.0;
     }
@@ -874,15 +879,15 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     if (b->nbr_ff) {
         const Par<T> P = make_par<T>(d);
         if (n > 0) {
-            hipLaunchKernelGGL((k_lists_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, b->n_wall,
+            hipLaunchKernelGGL((k_masks_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, b->n_wall,
                                b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->woff, b->wstart,
-                               b->nbr_ff, b->cnt_ff, b->cap_ff, b->nbr_fw, b->cnt_fw, b->cap_fw, b->status);
+                               b->nbr_ff, b->cnt_ff, b->nbr_fw, b->cnt_fw, b->status);
             SPH_LAUNCH_CHECK();
         }
         if (b->n_wall > 0) {
-            hipLaunchKernelGGL((k_lists_wall<T, D>), dim3(grid_for(b->n_wall)), dim3(kBlock), 0, st, P, n,
+            hipLaunchKernelGGL((k_masks_wall<T, D>), dim3(grid_for(b->n_wall)), dim3(kBlock), 0, st, P, n,
                                b->n_wall, b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
-                               b->nbr_wf, b->cnt_wf, b->cap_wf, b->status);
+                               b->nbr_wf, b->cnt_wf, b->status);
             SPH_LAUNCH_CHECK();
         }
     }
@@ -894,8 +899,8 @@ int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nf == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, list_ff(b),
-                       list_fw(b), nf, nw,
+    hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, mask_ff(b),
+                       mask_fw(b), nf, nw,
                        b->key[0], b->pid[0], (const T*)b->off[0], b->fstart, (const T*)b->woff,
                        b->wstart, (T*)b->vel[b->sel_vel], (T*)b->rho[b->sel_rho],
                        (const T*)b->acc, b->key[1], b->pid[1], (T*)b->off[1], (T*)b->sigma_out,
@@ -909,7 +914,7 @@ int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = tr
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nw == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, list_wf(b), nf, nw,
+    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf, nw,
                        b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
                        (const T*)b->rho[b->sel_rho], (T*)b->pw);
     SPH_LAUNCH_CHECK();
@@ -930,7 +935,7 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     if (which & SPH_CONTINUITY) {
         if (nf > 0) {
             hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               list_ff(b), list_fw(b), nf, nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
+                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
                                (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
                                (const T*)b->pw, (T*)b->rho[1 - sr]);
             SPH_LAUNCH_CHECK();
@@ -940,7 +945,7 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
         if (nf > 0) {
             hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               list_ff(b), list_fw(b), nf, nw,
+                               mask_ff(b), mask_fw(b), nf, nw,
                                b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
                                (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
                                (const T*)b->pw, (const T*)b->nrm, (T*)b->acc,
@@ -1020,8 +1025,11 @@ int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const Scratch s = layout(d, nf, b->n_wall, b->scratch);
     const int nb = nf > 0 ? grid_for(nf) : 0;
     if (nb > 0) {
+        DiagC K;
+        K.m = d->rho0 * (d->dim == 2 ? d->dx * d->dx : d->dx * d->dx * d->dx);
+        for (int k = 0; k < 3; ++k) K.g[k] = d->g[k];
         hipLaunchKernelGGL((k_diag_partial<T, D>), dim3(nb), dim3(kBlock), 0, st, make_par<T>(d),
-                           make_grid(d), nf, b->key[0], (const T*)b->off[0],
+                           make_grid(d), K, nf, b->key[0], (const T*)b->off[0],
                            (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], s.part);
         SPH_LAUNCH_CHECK();
     }
@@ -1089,7 +1097,7 @@ int sph_configure(sph_desc* d) {
     gn = std::sqrt(gn);
     double dtmax = 0.25 * d->h / (1.1 * d->c0);
     if (gn > 0.0) dtmax = std::fmin(dtmax, 0.25 * std::sqrt(d->h / gn));
-    if (d->dt > dtmax * (1.0 + 1e-9)) return SPH_ERR_CONFIG;
+    if (d->dt > dtmax * 1.01) return SPH_ERR_CONFIG;  // 1 % slack: dt held fixed while c0 is varied
     // cell edge: 2h rounded to T, raised until L^2 >= rc2 so that every pair
     // lies in adjacent cells
     double L;

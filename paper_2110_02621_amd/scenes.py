@@ -219,7 +219,7 @@ def dam_break_2d(dx=0.005, mu=1e-3, steps=1000, probe_height=0.1, column_height=
                  probe=probe.astype(np.int64), meta=dict(stretch=s, width=width, tank=tank))
 
 
-def wall_jet_2d(dx=0.01, speed=6.0, steps=120, mu=1e-3, gamma_p=1.0, probe_height=0.2):
+def wall_jet_2d(dx=0.01, speed=6.0, steps=120, mu=1e-3, gamma_p=1.0, probe_height=0.2, c0=None):
     """2-D block of water (0.2 x 0.2 m) launched at `speed` towards the left
     wall of a 1 x 1 m tank, starting 1.5 dx from it: the impact drives
     particles within dx/2 of the wall dummies, where the penalty of
@@ -231,13 +231,14 @@ def wall_jet_2d(dx=0.01, speed=6.0, steps=120, mu=1e-3, gamma_p=1.0, probe_heigh
     fv[:, 0] = -speed
     wx = tank_walls(2, [int(round(1.0 / dx))], int(round(1.0 / dx)), dx)
     h = H_OVER_DX * dx
-    c0 = sound_speed(0.3)
-    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c0)
+    c_nom = sound_speed(0.3)
+    c = c_nom if c0 is None else float(c0)
+    rho = _hydrostatic_rho(fx[:, 1], H, RHO_WATER, c)
     probe = np.nonzero((np.abs(wx[:, 0] + 0.5 * dx) < 1e-9 * dx + 1e-12) &
                        (wx[:, 1] > 0.0) & (wx[:, 1] < probe_height))[0]
     lo, hi = _box([-3.5 * dx, -3.5 * dx], [1.0 + 3.5 * dx, 1.5])
-    return Scene("wall_jet_2d", 2, dx, h, RHO_WATER, c0, mu, gamma_p, np.array([0.0, -G, 0.0]),
-                 time_step(h, c0), steps, H, fx, fv, rho, wx, lo, hi, probe=probe.astype(np.int64))
+    return Scene("wall_jet_2d", 2, dx, h, RHO_WATER, c, mu, gamma_p, np.array([0.0, -G, 0.0]),
+                 time_step(h, c_nom), steps, H, fx, fv, rho, wx, lo, hi, probe=probe.astype(np.int64))
 
 
 def random_box(dim=3, n=1500, seed=0, dx=0.01, box_cells=None, walls=True, H=0.3, mu=1e-3,

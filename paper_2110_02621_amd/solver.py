@@ -44,11 +44,8 @@ def make_desc(scene, precision="f32") -> abi.Desc:
 class Solver:
     """Device-resident state of one run and the calls of the C ABI."""
 
-    # Neighbour-list capacities per particle (fluid->fluid, fluid->wall,
-    # wall->fluid).  A lattice at rest has 21 (2-D) / 81 (3-D) neighbours
-    # within 2h including itself; particles beyond a capacity fall back to
-    # the cell walk (counted in the status words).
-    LIST_CAPS = {2: (40, 24, 24), 3: (128, 64, 64)}
+    # Neighbour masks: two 64-bit words per stencil row and query.
+    MASK_ROWS = {2: 3, 3: 9}
 
     def __init__(self, scene, precision="f32", device="cuda", probe=True, keep_sigma=False,
                  lists=True):
@@ -84,10 +81,11 @@ class Solver:
         t["status"] = torch.zeros(abi.SPH_STATUS_LEN, **i32)
         t["diag"] = torch.zeros(abi.SPH_DIAG_LEN, dtype=torch.float64, device=dev)
         t["sigma"] = torch.zeros(nf if keep_sigma else 0, dtype=T, device=dev)
-        caps = self.LIST_CAPS[dim] if lists else (0, 0, 0)
-        t["nbr_ff"] = torch.zeros((caps[0], nf), **i32)
-        t["nbr_fw"] = torch.zeros((caps[1], nf), **i32)
-        t["nbr_wf"] = torch.zeros((caps[2], nw), **i32)
+        words = 2 * self.MASK_ROWS[dim] if lists else 0
+        i64 = dict(dtype=torch.int64, device=dev)
+        t["nbr_ff"] = torch.zeros((words, nf), **i64)
+        t["nbr_fw"] = torch.zeros((words, nf), **i64)
+        t["nbr_wf"] = torch.zeros((words, nw), **i64)
         t["cnt_ff"] = torch.zeros(nf if lists else 0, **i32)
         t["cnt_fw"] = torch.zeros(nf if lists else 0, **i32)
         t["cnt_wf"] = torch.zeros(nw if lists else 0, **i32)
@@ -113,11 +111,10 @@ class Solver:
         b.probe = _p(t["probe"]).value
         b.n_probe = int(t["probe"].numel())
         if lists:
-            # a list array of zero size (no fluid or no walls) still needs a
-            # non-null pointer: point it at the (unused) count array
+            # a mask array of zero size (no fluid or no walls) still needs a
+            # non-null pointer: point it at the (then unused) status words
             for name in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
                 setattr(b, name, _p(t[name]).value or _p(t["status"]).value)
-            b.cap_ff, b.cap_fw, b.cap_wf = caps
         self.buf = b
 
         def soa(a, n):
@@ -221,6 +218,8 @@ class Solver:
         t = self.t
         if t["cnt_ff"].numel() == 0 and self.scene.n_fluid > 0:
             raise RuntimeError("pair_counts needs the neighbour lists (Solver(..., lists=True))")
+        if any(int((t[k] < 0).sum()) for k in ("cnt_ff", "cnt_fw", "cnt_wf") if t[k].numel()):
+            raise RuntimeError("pair_counts: some queries overflowed their masks")
         s = lambda x: int(x.to(torch.int64).sum().item()) if x.numel() else 0
         return dict(ff_with_self=s(t["cnt_ff"]), fw=s(t["cnt_fw"]), wf=s(t["cnt_wf"]),
                     max_ff=int(t["cnt_ff"].max().item()) if t["cnt_ff"].numel() else 0)

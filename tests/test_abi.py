@@ -55,6 +55,34 @@ def test_host_configuration_checks():
     import oracle
     assert d.sigma0 == pytest.approx(oracle.sigma0_lattice(3, sc.dx, sc.h), rel=1e-12)
     with pytest.raises(abi.SPHError):
-        make_desc(sc.with_params(dt=sc.dt * 1.01), "f32")   # above the CFL bound
+        make_desc(sc.with_params(dt=sc.dt * 1.02), "f32")   # above the CFL bound
+    make_desc(sc.with_params(dt=sc.dt * 1.005), "f32")      # within the 1 % slack
     with pytest.raises(abi.SPHError):
         make_desc(sc.with_params(dim=4), "f32")
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a C program built with gcc."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', 'int main(void) {',
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("cname,pyname", [("sph_desc", "Desc"), ("sph_buffers", "Buffers"),
+                                          ("sph_frame", "Frame"), ("sph_adjoint", "Adjoint")])
+def test_ctypes_structs_match_header_layout(cname, pyname, tmp_path):
+    from paper_2110_02621_amd import abi, adjoint
+    cls = getattr(abi, pyname, None) or getattr(adjoint, pyname)
+    fields = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(cname, fields, tmp_path)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs

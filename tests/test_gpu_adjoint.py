@@ -39,8 +39,7 @@ def make(base, theta, **kw):
     if base == "dam":
         return scenes.dam_break_2d(mu=mu, gamma_p=gp, c0=c0, column_height=H, **kw)
     if base == "jet":
-        sc = scenes.wall_jet_2d(mu=mu, gamma_p=gp, **kw)
-        return sc.with_params(c0=c0)
+        return scenes.wall_jet_2d(mu=mu, gamma_p=gp, c0=c0, **kw)
     raise ValueError(base)
 
 
@@ -87,9 +86,11 @@ def fd_oracle(base, th, steps, rel=STEP, kw=None):
 
 
 def compare(g, fd, th, rtol, label, zero_atol=1e-9):
-    # relative per component; a component whose differences vanish exactly
-    # (no penalty contact) must vanish in the adjoint too
-    print(f"  {label}: adjoint {g}  fd {fd}", flush=True)
+    # relative per component (rtol may be a per-component sequence); a
+    # component whose differences vanish exactly (no penalty contact) must
+    # vanish in the adjoint too
+    print(f"  {label}: adjoint {g}  fd {fd}  rel {np.abs(g / np.where(fd == 0, 1, fd) - 1)}", flush=True)
+    rt = np.broadcast_to(np.asarray(rtol, dtype=float), (4,))
     ref = np.nanmax(np.abs(np.nan_to_num(fd) * th))
     for k in range(4):
         if np.isnan(fd[k]):
@@ -97,7 +98,7 @@ def compare(g, fd, th, rtol, label, zero_atol=1e-9):
         if fd[k] == 0.0:
             assert abs(g[k] * th[k]) <= zero_atol * ref, (NAMES[k], g[k])
         else:
-            assert abs(g[k] - fd[k]) <= rtol * abs(fd[k]), (NAMES[k], g[k], fd[k], abs(g[k] / fd[k] - 1))
+            assert abs(g[k] - fd[k]) <= rt[k] * abs(fd[k]), (NAMES[k], g[k], fd[k], abs(g[k] / fd[k] - 1))
 
 
 def test_adjoint_fp64_matches_gpu_finite_differences(adj):
@@ -144,7 +145,14 @@ def test_adjoint_fp32_matches_oracle_finite_differences(adj):
     st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe).step(steps)
     print(f"  J gpu {r['J']:.9e} oracle {st.J:.9e}", flush=True)
     assert abs(r["J"] - st.J) <= 1e-4 * abs(st.J)
-    compare(g, fd, th, 1e-3, "dam f32 vs oracle")
+    # mu acts through the viscous term, a second difference of the velocity
+    # field: in an FP32 forward its relative error is ~ eps32 (L/dx)^2 ~ 1e-3
+    # here, which bounds any FP32 gradient with respect to mu; the FP64 run
+    # below pins mu tightly.
+    compare(g, fd, th, (5e-3, 1e-3, 1e-3, 1e-3), "dam f32 vs oracle")
+    r64 = adj.probe_gradient(sc, precision="f64", K=25)
+    g64 = np.array([r64["grad"][n] for n in NAMES])
+    compare(g64, fd, th, 2e-5, "dam f64 vs oracle")
 
 
 def test_autograd_function(adj):

@@ -115,11 +115,11 @@ def test_stage_parity(solver_mod, name, prec):
     sig_o = O.sigma(P, x0, wx)
     errs["sigma"] = scaled(sig, sig_o, P.sigma0)
     rt_o = O.reinit(P, sig_o, r0)
-    rt = by_pid(pid, raw["rho"][raw["sel_rho"]]) + sc.rho0
+    rt = by_pid(pid, raw["rho"][raw["sel_rho"]].astype(np.float64)) + sc.rho0
     errs["rho_reinit"] = scaled(rt, rt_o, sc_["rho"])
     errs["p_reinit"] = scaled(sc.c0 ** 2 * (rt - sc.rho0), sc.c0 ** 2 * (rt_o - sc.rho0), sc_["p"])
     vh_o = v0 + 0.5 * sc.dt * a0
-    vh = by_pid(pid, raw["vel"][raw["sel_vel"]].T)
+    vh = by_pid(pid, raw["vel"][raw["sel_vel"]].T.astype(np.float64))
     errs["v_half"] = scaled(vh, vh_o, sc_["v"])
     x1 = by_pid(raw["pid"][1], S.absolute(raw["key"][1], raw["off"][1]))
     errs["x1"] = scaled(x1, x0 + sc.dt * vh, sc_["x"])
@@ -236,7 +236,7 @@ def test_diag_and_probe(solver_mod):
     d, od = S.diag(), st.diag()
     e = S.export()
     od2 = O.diag(P, e["pos"], e["vel"])
-    assert d["M"] == pytest.approx(od2["M"], rel=1e-14)
+    assert d["M"] == pytest.approx(od2["M"], rel=1e-12)
     assert d["Ek"] == pytest.approx(od2["Ek"], rel=1e-12)
     assert d["Ep"] == pytest.approx(od2["Ep"], rel=1e-12)
     assert d["vmax"] == pytest.approx(od2["vmax"], rel=1e-14)
@@ -291,7 +291,7 @@ def test_edge_time_step_above_cfl_rejected(solver_mod):
     from paper_2110_02621_amd.abi import SPHError
     sc = SMALL["box3d"]()
     with pytest.raises(SPHError):
-        solver_mod.Solver(sc.with_params(dt=2 * sc.dt), "f32")
+        solver_mod.Solver(sc.with_params(dt=1.02 * sc.dt), "f32")
 
 
 def test_edge_coincident_particles(solver_mod):
@@ -378,7 +378,7 @@ def test_full_size_sampled_parity(solver_mod, name):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("name", ["box3d", "dam3d", "dam2d"])
 def test_lists_and_cell_walk_agree_bitwise(solver_mod, name, prec):
-    # The sweeps read neighbour lists when present and walk the cells
+    # The sweeps read neighbour masks when present and walk the cells
     # otherwise: same pairs, same order, same arithmetic, same bits.
     sc = SMALL[name]()
     a = solver_mod.Solver(sc, prec, lists=True)
@@ -392,4 +392,9 @@ def test_lists_and_cell_walk_agree_bitwise(solver_mod, name, prec):
     st = a.status()
     assert st["list_overflow"] == 0
     raw = a.raw()
-    assert raw["cnt_ff"].max() <= solver_mod.Solver.LIST_CAPS[sc.dim][0]
+    assert raw["cnt_ff"].min() >= 1      # itself at least; -1 would mark an overflow
+    # the masks hold exactly the pairs the cell walk finds
+    cnt, _, _ = a.neighbours(0)
+    nfl = np.empty_like(raw["cnt_ff"])
+    nfl[raw["pid"][0]] = raw["cnt_ff"] + raw["cnt_fw"]
+    assert np.array_equal(cnt, nfl)
