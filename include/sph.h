@@ -276,6 +276,10 @@ typedef struct sph_frame {
     const void *vh;           /* T[dim][n_fluid] velocity of the drift into r^n (frame 0: v^0) */
     const void *rt;           /* T[n_fluid] reinitialised density of step n-1, minus rho0 */
     const void *pw;           /* T[n_wall] wall pressure at r^n (frame 0: the initial one) */
+    /* optional neighbour masks and counts of this state (see sph_buffers);
+     * when all are given the backward sweeps visit them instead of walking */
+    const uint64_t *nbr_ff, *nbr_fw, *nbr_wf;
+    const int32_t *cnt_ff, *cnt_fw, *cnt_wf;
 } sph_frame;
 
 /* Adjoint state (device, FP64, particle-id order) and workspace. */
@@ -290,6 +294,15 @@ typedef struct sph_adjoint {
 } sph_adjoint;
 
 size_t sph_adjoint_work_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
+
+/* One forward step (exactly sph_step with nsteps = 1) that also records
+ * the frames the backward needs: sigma at r^n into sigma_cur (T[n_fluid],
+ * the current sorted order) and the state at r^{n+1} into the arrays of
+ * next (written through its pointers, which must be distinct device
+ * buffers of the sizes stated in sph_frame; the mask fields are copied only
+ * when buf has masks and next provides them). */
+int sph_step_frame(const sph_desc *desc, sph_buffers *buf, void *sigma_cur, sph_frame *next,
+                   void *stream);
 
 /* Zeroes the adjoint state and theta. */
 int sph_adjoint_zero(const sph_desc *desc, const sph_buffers *buf, sph_adjoint *adj, void *stream);

@@ -23,7 +23,7 @@ EXPORTED = ["sph_configure", "sph_scratch_bytes", "sph_init", "sph_build_cells",
             "sph_wall_bc", "sph_forces", "sph_step", "sph_diag", "sph_export", "sph_export_walls",
             "sph_neighbours", "sph_strerror",
             "sph_adjoint_work_bytes", "sph_adjoint_zero", "sph_forces_bwd", "sph_wall_bc_bwd",
-            "sph_density_bwd", "sph_step_bwd", "sph_init_bwd"]
+            "sph_density_bwd", "sph_step_bwd", "sph_init_bwd", "sph_step_frame"]
 
 
 class Desc(C.Structure):

@@ -26,7 +26,9 @@ THETA_NAMES = ("mu", "gamma_p", "c0", "H")
 class Frame(C.Structure):
     _fields_ = [("key", C.c_void_p), ("pid", C.c_void_p), ("off", C.c_void_p), ("fstart", C.c_void_p),
                 ("rho", C.c_void_p), ("sigma", C.c_void_p), ("vh", C.c_void_p), ("rt", C.c_void_p),
-                ("pw", C.c_void_p)]
+                ("pw", C.c_void_p),
+                ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
+                ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p)]
 
 
 class Adjoint(C.Structure):
@@ -46,6 +48,8 @@ def _declare(L):
     for name in ("sph_forces_bwd", "sph_wall_bc_bwd", "sph_density_bwd"):
         getattr(L, name).argtypes = [dp, bp, fp, ap, vp]
     L.sph_step_bwd.argtypes = [dp, bp, fp, fp, ap, vp]
+    L.sph_step_frame.argtypes = [dp, bp, vp, fp, vp]
+    L.sph_step_frame.restype = C.c_int
     L.sph_init_bwd.argtypes = [dp, bp, fp, C.c_double, ap, vp]
     for name in ("sph_adjoint_zero", "sph_forces_bwd", "sph_wall_bc_bwd", "sph_density_bwd",
                  "sph_step_bwd", "sph_init_bwd"):
@@ -77,46 +81,54 @@ def load_state(S, st):
         S.t[k].copy_(st[k])
 
 
-class FrameStore:
-    """Per-step frames of one recomputed segment (device tensors)."""
+MASKS = ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf")
 
-    def __init__(self):
-        self.t = {}
 
-    def struct(self):
-        f = Frame()
+class FramePool:
+    """Device storage for the frames of one segment (reused by every
+    segment): frame k holds the state at the segment's step k."""
+
+    def __init__(self, S, nframes):
+        t = S.t
+        self.frames = []
+        for k in range(nframes):
+            f = {"sigma": torch.empty_like(t["rho"][0])}
+            if k > 0:
+                for name, src in (("key", t["key"][0]), ("pid", t["pid"][0]), ("off", t["off"][0]),
+                                  ("fstart", t["fstart"]), ("vh", t["vel"][0]), ("rt", t["rho"][0]),
+                                  ("rho", t["rho"][0]), ("pw", t["pw"])):
+                    f[name] = torch.empty_like(src)
+                for name in MASKS:
+                    f[name] = torch.empty_like(t[name])
+            self.frames.append(f)
+
+    @staticmethod
+    def struct(f):
+        fr = Frame()
         for name, _ in Frame._fields_:
-            v = self.t.get(name)
-            setattr(f, name, _p(v).value if v is not None else None)
-        return f
+            v = f.get(name)
+            setattr(fr, name, (_p(v).value or None) if v is not None else None)
+        return fr
 
 
-def recompute_segment(S, start_state, nsteps, first_frame_extra=None):
-    """Restore `start_state`, run nsteps steps stage by stage and return the
-    nsteps + 1 frames (frame k = state at step start + k)."""
+def recompute_segment(S, pool, start_state, nsteps, first_frame_extra=None):
+    """Restore `start_state` and rerun nsteps steps, recording frames
+    0..nsteps into the pool (frame 0 refers to the checkpoint's arrays)."""
+    L = S.lib
     load_state(S, start_state)
-    frames = [FrameStore() for _ in range(nsteps + 1)]
-    f0 = frames[0].t
-    for k in ("key", "pid", "off", "fstart", "rho"):
+    f0 = pool.frames[0]
+    for k in ("key", "pid", "off", "fstart", "rho") + MASKS:
         f0[k] = start_state[k]
+    f0.pop("vh", None)
+    f0.pop("pw", None)
     if first_frame_extra:
         f0.update(first_frame_extra)
+    stream = S._stream()
     for n in range(nsteps):
-        S.density()
-        frames[n].t["sigma"] = S.t["sigma"].clone()
-        S.build_cells()
-        c = _cur(S)
-        nxt = frames[n + 1].t
-        for k in ("key", "pid", "off", "fstart"):
-            nxt[k] = c[k].clone()
-        nxt["vh"] = c["vel"].clone()
-        nxt["rt"] = c["rho"].clone()
-        S.wall_bc()
-        nxt["pw"] = S.t["pw"].clone()
-        S.continuity()
-        nxt["rho"] = _cur(S)["rho"].clone()
-        S.momentum()
-    return frames
+        nxt = FramePool.struct(pool.frames[n + 1])
+        check(L.sph_step_frame(C.byref(S.desc), C.byref(S.buf), _p(pool.frames[n]["sigma"]),
+                               C.byref(nxt), stream), "sph_step_frame")
+    return [FramePool.struct(f) for f in pool.frames[:nsteps + 1]]
 
 
 def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", return_timings=False):
@@ -155,21 +167,20 @@ def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", retu
     adj.work = (work.data_ptr() + 255) & ~255
     adj.work_bytes = wb
     stream = S._stream()
+    pool = FramePool(S, min(K, steps) + 1)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     check(L.sph_adjoint_zero(C.byref(S.desc), C.byref(S.buf), C.byref(adj), stream), "sph_adjoint_zero")
     for seg in reversed(range(len(ckpts))):
         start, st = ckpts[seg]
         k = min(K, steps - start)
-        frames = recompute_segment(S, st, k, init_extra if start == 0 else None)
-        structs = [f.struct() for f in frames]
+        structs = recompute_segment(S, pool, st, k, init_extra if start == 0 else None)
         for n in reversed(range(k)):
             check(L.sph_step_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[n]),
                                  C.byref(structs[n + 1]), C.byref(adj), stream), "sph_step_bwd")
         if start == 0:
             check(L.sph_init_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[0]), float(scene.H),
                                  C.byref(adj), stream), "sph_init_bwd")
-        del frames, structs
     grad = theta.cpu().numpy().copy()
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t1

@@ -72,6 +72,10 @@ AdjPar make_adj(const sph_desc* d) {
     return Q;
 }
 
+NbrMask fmask(const uint64_t* m, const int32_t* c, int64_t n) {
+    return (m && c) ? NbrMask{m, c, n} : NbrMask{nullptr, nullptr, 0};
+}
+
 struct PairGeo {
     double d[3], r2, r, t, F, Fpr, W;  // Fpr = F'(r)/r
 };
@@ -150,7 +154,7 @@ __device__ __forceinline__ void limiter(double J, double c, double& beta, double
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_mom_bwd(Par<T> P, AdjPar Q, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_mom_bwd(Par<T> P, AdjPar Q, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
               const int32_t* __restrict__ pid, const T* __restrict__ off,
               const int32_t* __restrict__ fstart, const T* __restrict__ vh,
               const T* __restrict__ rp, const int32_t* __restrict__ wkey,
@@ -174,8 +178,8 @@ __global__ void __launch_bounds__(kBlock)
         const double ri = Q.rho0 + (double)rp[i];
         const double pi_ = Q.c2 * (double)rp[i];
         double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, gr = 0.0;
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi,
-                             [&](int j, const T dT[3], T r2T, uint32_t) {
+        visit<T, D>(P, LF, i, fstart, off, off + nf, off + 2 * nf, c, oi,
+                    [&](int j, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;
             const PairGeo G = geo<D>(Q, dT);
             const int64_t pj = pid[j];
@@ -217,8 +221,8 @@ __global__ void __launch_bounds__(kBlock)
             th[SPH_THETA_C0] += -2.0 * C * ai * Nc / S;
         });
         if (nw > 0)
-            for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                                 [&](int w, const T dT[3], T r2T, uint32_t) {
+            visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                        [&](int w, const T dT[3], T r2T, uint32_t) {
                 if (!(r2T > T(0))) return;
                 const PairGeo G = geo<D>(Q, dT);
                 const double pwv = (double)pw[w];
@@ -282,7 +286,7 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_cont_bwd(Par<T> P, AdjPar Q, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_cont_bwd(Par<T> P, AdjPar Q, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                const int32_t* __restrict__ pid, const T* __restrict__ off,
                const int32_t* __restrict__ fstart, const T* __restrict__ vh,
                const T* __restrict__ rt, const T* __restrict__ woff,
@@ -302,8 +306,8 @@ __global__ void __launch_bounds__(kBlock)
         const double kap = Q.dt * rpb[p];
         const double psi_i = 2.0 * Q.m * kap * ri;
         double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, gr = 0.0, sumG = 0.0;
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi,
-                             [&](int j, const T dT[3], T r2T, uint32_t) {
+        visit<T, D>(P, LF, i, fstart, off, off + nf, off + 2 * nf, c, oi,
+                    [&](int j, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;
             const PairGeo G = geo<D>(Q, dT);
             const int64_t pj = pid[j];
@@ -327,8 +331,8 @@ __global__ void __launch_bounds__(kBlock)
             th[SPH_THETA_C0] += psi_i * G.F * dp * G.r / (rj * S * Q.c2);
         });
         if (nw > 0)
-            for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                                 [&](int w, const T dT[3], T r2T, uint32_t) {
+            visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                        [&](int w, const T dT[3], T r2T, uint32_t) {
                 if (!(r2T > T(0))) return;
                 const PairGeo G = geo<D>(Q, dT);
                 const double pwv = (double)pw[w];
@@ -364,7 +368,7 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_wall_bwd(Par<T> P, AdjPar Q, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
+    k_wall_bwd(Par<T> P, AdjPar Q, NbrMask LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
                const int32_t* __restrict__ wpid, const T* __restrict__ woff,
                const T* __restrict__ nrm, const T* __restrict__ pw, const int32_t* __restrict__ pid,
                const T* __restrict__ off, const int32_t* __restrict__ fstart,
@@ -384,8 +388,8 @@ __global__ void __launch_bounds__(kBlock)
         for (int k = 0; k < D; ++k) n[k] = (double)nrm[k * nw + w];
     double SW = 0.0, pbar = 0.0;
     if (nf > 0)
-        for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow,
-                             [&](int f, const T dT[3], T r2T, uint32_t) {
+        visit<T, D>(P, LWF, w, fstart, off, off + nf, off + 2 * nf, c, ow,
+                    [&](int f, const T dT[3], T r2T, uint32_t) {
             const PairGeo G0 = geo<D>(Q, dT);
             SW += G0.W;
             if (!(r2T > T(0))) return;
@@ -444,7 +448,7 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_pw_bwd(Par<T> P, AdjPar Q, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_pw_bwd(Par<T> P, AdjPar Q, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
              const int32_t* __restrict__ pid, const T* __restrict__ off,
              const T* __restrict__ rho, const T* __restrict__ woff,
              const int32_t* __restrict__ wstart, const T* __restrict__ pw,
@@ -460,8 +464,8 @@ __global__ void __launch_bounds__(kBlock)
         const double rf = Q.rho0 + (double)rho[i];
         const double pf_ = Q.c2 * (double)rho[i];
         double gx[3] = {0, 0, 0}, gr = 0.0;
-        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int w, const T dT[3], T r2T, uint32_t) {
+        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                    [&](int w, const T dT[3], T r2T, uint32_t) {
             const double lw = lam[w];
             if (lw == 0.0) return;
             const PairGeo G = geo<D>(Q, dT);
@@ -518,7 +522,7 @@ __global__ void __launch_bounds__(kBlock)
 // Number density backward at r^n: xb_i += sum_j (sigb_i + sigb_j) F d + sum_w sigb_i F d.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_sigma_bwd(Par<T> P, AdjPar Q, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
+    k_sigma_bwd(Par<T> P, AdjPar Q, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                 const int32_t* __restrict__ pid, const T* __restrict__ off,
                 const int32_t* __restrict__ fstart, const T* __restrict__ woff,
                 const int32_t* __restrict__ wstart, const double* __restrict__ sigb,
@@ -531,16 +535,16 @@ __global__ void __launch_bounds__(kBlock)
     const T oi[3] = {off[i], off[nf + i], D == 3 ? off[2 * nf + i] : T(0)};
     const double si = sigb[p];
     double gx[3] = {0, 0, 0};
-    for_neighbours<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi,
-                         [&](int j, const T dT[3], T r2T, uint32_t) {
+    visit<T, D>(P, LF, i, fstart, off, off + nf, off + 2 * nf, c, oi,
+                [&](int j, const T dT[3], T r2T, uint32_t) {
         if (!(r2T > T(0))) return;
         const PairGeo G = geo<D>(Q, dT);
         const double s = si + sigb[pid[j]];
         for (int k = 0; k < D; ++k) gx[k] += s * G.F * G.d[k];
     });
     if (nw > 0)
-        for_neighbours<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int, const T dT[3], T r2T, uint32_t) {
+        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
+                    [&](int, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;
             const PairGeo G = geo<D>(Q, dT);
             for (int k = 0; k < D; ++k) gx[k] += si * G.F * G.d[k];
@@ -649,14 +653,16 @@ int forces_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, sp
     const AdjPar Q = make_adj(d);
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     const int nb = grid_for(nf);
-    hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+    hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
+                       fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, b->wkey,
                        (const T*)b->woff, b->wstart, (const T*)f->pw, (const T*)b->nrm, a->ab, a->vb,
                        Q.half_dt, a->rhob, a->xb, w.vhb, w.rpb, w.part);
     SPH_LAUNCH_CHECK();
     int rc = reduce_theta(w, nb, a->theta, st);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_cont_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+    hipLaunchKernelGGL((k_cont_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
+                       fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rt, (const T*)b->woff,
                        b->wstart, (const T*)f->pw, w.rpb, a->xb, w.vhb, w.rtb, w.part);
     SPH_LAUNCH_CHECK();
@@ -671,7 +677,8 @@ int wall_bc_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, s
     const Par<T> P = make_par<T>(d);
     const AdjPar Q = make_adj(d);
     const AdjWork w = adj_layout(d, nf, nw, a->work);
-    hipLaunchKernelGGL((k_wall_bwd<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, Q, nf, nw,
+    hipLaunchKernelGGL((k_wall_bwd<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, Q,
+                       fmask(f->nbr_wf, f->cnt_wf, nw), nf, nw,
                        b->wkey, b->wpid, (const T*)b->woff, (const T*)b->nrm, (const T*)f->pw, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, (const T*)f->rt,
                        nf > 0 ? a->ab : nullptr, a->vb, Q.half_dt, nf > 0 ? w.rpb : nullptr,
@@ -679,7 +686,8 @@ int wall_bc_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, s
     SPH_LAUNCH_CHECK();
     if (nf == 0) return SPH_OK;
     const int nb = grid_for(nf);
-    hipLaunchKernelGGL((k_pw_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+    hipLaunchKernelGGL((k_pw_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_fw, f->cnt_fw, nf),
+                       nf, nw, f->key, f->pid,
                        (const T*)f->off, (const T*)f->rt, (const T*)b->woff, b->wstart, (const T*)f->pw,
                        w.lam, a->xb, w.rtb, w.part);
     SPH_LAUNCH_CHECK();
@@ -699,7 +707,8 @@ int density_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, s
                        (const T*)f->sigma, (const T*)f->rho, a->xb, w.vhb, w.rtb, a->vb, a->ab, w.sigb,
                        a->rhob);
     SPH_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sigma_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+    hipLaunchKernelGGL((k_sigma_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
+                       fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)b->woff, b->wstart, w.sigb, a->xb);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
@@ -715,7 +724,8 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     const int nb = grid_for(nf);
     // a^0 = MOM(r^0, v^0, rho^0, p_w^0): Abar = ab (no kick), rho adjoint in place
-    hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+    hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
+                       fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, b->wkey,
                        (const T*)b->woff, b->wstart, (const T*)f->pw, (const T*)b->nrm, a->ab,
                        (const double*)nullptr, 0.0, a->rhob, a->xb, w.tmp, a->rhob, w.part);
@@ -724,13 +734,15 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
     if (rc) return rc;
     // p_w^0 = PW(r^0, rho^0): momentum part only, no probe term
     if (nw > 0) {
-        hipLaunchKernelGGL((k_wall_bwd<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, Q, nf, nw,
+        hipLaunchKernelGGL((k_wall_bwd<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, Q,
+                           fmask(f->nbr_wf, f->cnt_wf, nw), nf, nw,
                            b->wkey, b->wpid, (const T*)b->woff, (const T*)b->nrm, (const T*)f->pw, f->pid,
                            (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho,
                            (const T*)f->rho, a->ab, (const double*)nullptr, 0.0, (const double*)nullptr,
                            (const int32_t*)nullptr, 0, w.lam);
         SPH_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_pw_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, nf, nw, f->key, f->pid,
+        hipLaunchKernelGGL((k_pw_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q,
+                           fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                            (const T*)f->off, (const T*)f->rho, (const T*)b->woff, b->wstart,
                            (const T*)f->pw, w.lam, a->xb, a->rhob, w.part);
         SPH_LAUNCH_CHECK();

@@ -1019,6 +1019,51 @@ int step_t(const sph_desc* d, sph_buffers* b, int nsteps, hipStream_t st) {
     return SPH_OK;
 }
 
+// Device-to-device copy of n bytes (skipped when either side is absent).
+inline int copy_d2d(const void* dst, const void* src, size_t n, hipStream_t st) {
+    if (!dst || !src || n == 0) return SPH_OK;
+    return hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? SPH_OK
+               : SPH_ERR_LAUNCH;
+}
+
+template <typename T, int D>
+int step_frame_t(const sph_desc* d, sph_buffers* b, void* sigma_cur, sph_frame* nx, hipStream_t st) {
+    const int64_t nf = b->n_fluid, nw = b->n_wall;
+    const size_t ts = sizeof(T);
+    void* keep = b->sigma_out;
+    b->sigma_out = sigma_cur;
+    int rc = density_t<T, D>(d, b, st);
+    b->sigma_out = keep;
+    if (!rc) rc = build_cells_t<T, D>(d, b, st);
+    if (rc) return rc;
+    const size_t rows = d->dim == 3 ? 9 : 3;
+    rc = copy_d2d(nx->key, b->key[0], 4 * (size_t)nf, st);
+    if (!rc) rc = copy_d2d(nx->pid, b->pid[0], 4 * (size_t)nf, st);
+    if (!rc) rc = copy_d2d(nx->off, b->off[0], ts * D * (size_t)nf, st);
+    if (!rc) rc = copy_d2d(nx->fstart, b->fstart, 4 * (size_t)(d->n_cells + 1), st);
+    if (!rc) rc = copy_d2d(nx->vh, b->vel[b->sel_vel], ts * D * (size_t)nf, st);
+    if (!rc) rc = copy_d2d(nx->rt, b->rho[b->sel_rho], ts * (size_t)nf, st);
+    if (!rc && b->nbr_ff && nx->nbr_ff && nx->nbr_fw && nx->nbr_wf && nx->cnt_ff && nx->cnt_fw && nx->cnt_wf) {
+        const size_t wf = 8 * 2 * rows * (size_t)nf, ww = 8 * 2 * rows * (size_t)nw;
+        rc = copy_d2d(nx->nbr_ff, b->nbr_ff, wf, st);
+        if (!rc) rc = copy_d2d(nx->nbr_fw, b->nbr_fw, wf, st);
+        if (!rc) rc = copy_d2d(nx->nbr_wf, b->nbr_wf, ww, st);
+        if (!rc) rc = copy_d2d(nx->cnt_ff, b->cnt_ff, 4 * (size_t)nf, st);
+        if (!rc) rc = copy_d2d(nx->cnt_fw, b->cnt_fw, 4 * (size_t)nf, st);
+        if (!rc) rc = copy_d2d(nx->cnt_wf, b->cnt_wf, 4 * (size_t)nw, st);
+    }
+    if (!rc) rc = wall_bc_t<T, D>(d, b, st);
+    if (!rc) rc = copy_d2d(nx->pw, b->pw, ts * (size_t)nw, st);
+    if (!rc) rc = forces_t<T, D>(d, b, SPH_CONTINUITY, st);
+    if (!rc) rc = copy_d2d(nx->rho, b->rho[b->sel_rho], ts * (size_t)nf, st);
+    if (!rc) rc = forces_t<T, D>(d, b, SPH_MOMENTUM, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, st, b->diag);
+    SPH_LAUNCH_CHECK();
+    return SPH_OK;
+}
+
 template <typename T, int D>
 int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int64_t nf = b->n_fluid;
@@ -1191,6 +1236,16 @@ int sph_step(const sph_desc* d, sph_buffers* b, int nsteps, void* stream) {
     SPH_ENTRY_CHECKS();
     if (nsteps < 0) return SPH_ERR_ARG;
     return SPH_DISPATCH(step_t, d, b, nsteps, st);
+}
+
+int sph_step_frame(const sph_desc* d, sph_buffers* b, void* sigma_cur, sph_frame* next, void* stream) {
+    SPH_ENTRY_CHECKS();
+    if (!next) return SPH_ERR_ARG;
+    if (b->n_fluid > 0 && (!sigma_cur || !next->key || !next->pid || !next->off || !next->fstart ||
+                           !next->vh || !next->rt || !next->rho))
+        return SPH_ERR_ARG;
+    if (b->n_wall > 0 && !next->pw) return SPH_ERR_ARG;
+    return SPH_DISPATCH(step_frame_t, d, b, sigma_cur, next, st);
 }
 
 int sph_diag(const sph_desc* d, sph_buffers* b, void* stream) {
