@@ -31,18 +31,21 @@ METRIC = "particle-steps/s (3-D dam break, 4M particles, FP32 vs FP64) + adjoint
 # square root, reciprocal and reciprocal square root count as one each.
 # Culled candidates (r >= 2h) are not counted.
 FLOPS_PAIR = {
-    "density": 22,        # sigma += W(r)
     "wall_bc": 33,        # sum W, sum p W, sum rho r W
     "continuity_ff": 39,  # Eq. (9) with the Riemann intermediate velocity
     "continuity_fw": 36,
     "momentum_ff": 68,    # Eq. (10) with p* of Eq. (8), viscous term
     "momentum_fw": 64,    # Eq. (11) p*, viscous, penalty test
+    "momentum_sigma": 14,  # sigma += W(r) (compensated) for the next step, every pair incl. self
 }
-# Compulsory HBM bytes per fluid particle of the cell sort in FP32
+# Compulsory HBM bytes per fluid particle in FP32 of the cell sort
 # (histogram 16, placement 16, in-cell ordering 8, gather 76) and per cell
-# (count fill, scan read/write, cell table reads): see the design notes.
+# (count fill, scan read/write, cell table reads); of the density update
+# (reads sigma, rho, v, dv/dt, offset, key, id: 52; writes rho, v, offset,
+# key, id: 36).
 SORT_BYTES_PARTICLE = 116
 SORT_BYTES_CELL = 24
+DENSITY_BYTES_PARTICLE = 88
 
 PEAK_FP32 = 157.3e12      # MI355X published FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, one FMA per lane per clock
@@ -58,6 +61,7 @@ def parse():
     ap.add_argument("--obstacles", type=int, default=8)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-4m", action="store_true", help="skip the dx = 0.003 m (4M fluid) point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
@@ -130,26 +134,45 @@ def main():
           file=sys.stderr, flush=True)
 
     flops = {
-        "density": FLOPS_PAIR["density"] * (pc["all_with_self"]),
         "wall_bc": FLOPS_PAIR["wall_bc"] * pc["wf"],
         "continuity": FLOPS_PAIR["continuity_ff"] * pc["ff"] + FLOPS_PAIR["continuity_fw"] * pc["fw"],
-        "momentum": FLOPS_PAIR["momentum_ff"] * pc["ff"] + FLOPS_PAIR["momentum_fw"] * pc["fw"],
+        "momentum": (FLOPS_PAIR["momentum_ff"] * pc["ff"] + FLOPS_PAIR["momentum_fw"] * pc["fw"]
+                     + FLOPS_PAIR["momentum_sigma"] * pc["all_with_self"]),
     }
     kernels = {}
     for k, f in flops.items():
         t = stage[k] * 1e-3
         kernels[k] = dict(ms=round(stage[k], 4), tflops=round(f / t / 1e12, 3),
                           alu_frac=round(f / t / PEAK_FP32, 4))
+    dens_bytes = DENSITY_BYTES_PARTICLE * nf
+    kernels["density"] = dict(ms=round(stage["density"], 4),
+                              gbps=round(dens_bytes / (stage["density"] * 1e-3) / 1e9, 1),
+                              hbm_frac=round(dens_bytes / (stage["density"] * 1e-3) / PEAK_HBM, 4))
+    # the cell stage is the counting sort plus the neighbour-mask build;
+    # the bytes below are the sort's alone (the mask build culls candidates)
     sort_bytes = SORT_BYTES_PARTICLE * nf + SORT_BYTES_CELL * int(S.desc.n_cells)
-    kernels["sort"] = dict(ms=round(stage["sort"], 4),
-                           gbps=round(sort_bytes / (stage["sort"] * 1e-3) / 1e9, 1),
-                           hbm_frac=round(sort_bytes / (stage["sort"] * 1e-3) / PEAK_HBM, 4))
-    dom = max(("density", "wall_bc", "continuity", "momentum"), key=lambda k: stage[k])
+    kernels["cells"] = dict(ms=round(stage["sort"], 4),
+                            sort_gbps_lower_bound=round(sort_bytes / (stage["sort"] * 1e-3) / 1e9, 1))
+    dom = max(("continuity", "momentum"), key=lambda k: stage[k])
     ach = flops[dom] / (stage[dom] * 1e-3)
     roofline = dict(bound="alu", achieved=round(ach / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
                     frac=round(ach / PEAK_FP32, 4), traffic=None, kernel=dom)
     del S
     torch.cuda.empty_cache()
+
+    # the same dam break at dx = 0.003 m: exactly 4,000,000 fluid particles
+    m4 = None
+    if not args.no_4m:
+        sc4m = scenes.dam_break_3d(dx=0.003, obstacles=args.obstacles, seed=0, steps=args.steps)
+        k4 = max(10, args.steps // 2)
+        S4, wall4, _ = timed_run(solver, sc4m, "f32", k4, max(2, args.warmup // 2))
+        m4 = dict(workload=f"3-D dam break with {args.obstacles} seeded obstacles, dx=0.003 m, "
+                           f"{sc4m.n_fluid} fluid + {sc4m.n_wall} wall",
+                  value=(sc4m.n_fluid + sc4m.n_wall) * k4 / wall4, ms_per_step=1e3 * wall4 / k4, steps=k4,
+                  status=S4.status())
+        print(f"[bench] 4M f32 {m4['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        del S4
+        torch.cuda.empty_cache()
 
     fp64 = None
     if not args.no_fp64:
@@ -219,6 +242,7 @@ def main():
                    "n_fluid": nf, "n_wall": nw, "dx": args.dx, "obstacles": args.obstacles,
                    "parallelism": "single GPU"},
         "fluid_particle_steps_per_s": nf * args.steps / wall,
+        "fp32_4M": m4,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
         "adjoint_fwd_ratio": adj["ratio"] if adj else None,

@@ -133,7 +133,12 @@ typedef struct sph_buffers {
     void *sigma_out;       /* optional T[n_fluid]: sph_density writes sigma_i (sorted order) */
     const int32_t *probe;  /* optional: wall ids of the probe patch (device) */
     int32_t n_probe;
-    int32_t reserved;
+    /* 1 when the scratch holds sigma_i of the current sorted positions,
+     * summed by the last momentum sweep (set by sph_forces(SPH_MOMENTUM),
+     * cleared by sph_init, sph_build_cells and sph_density); sph_density
+     * then reads it instead of summing again.  A caller that overwrites
+     * positions, cell tables or masks must set it to 0. */
+    int32_t sigma_ready;
     /* Optional neighbour masks (all three or none).  When given,
      * sph_build_cells fills them for the sorted state and every sweep reads
      * them instead of testing all stencil candidates (same pairs, same
@@ -142,7 +147,9 @@ typedef struct sph_buffers {
      * dy+1 in 2-D) the words mask[(2*r + w) * n_query + q], w = 0, 1, have
      * bit b set when candidate base_r + 64*w + b of the row's index range is
      * a neighbour.  count[q] is the number of neighbours, or -1 when a row
-     * had more than 128 candidates (that query then walks the cells). */
+     * had more than 128 candidates (that query then walks the cells).  Words
+     * of rows without candidates, and word 1 of rows of at most 64, are left
+     * unwritten (never read). */
     uint64_t *nbr_ff;  /* fluid -> fluid, uint64[rows][2][n_fluid] */
     uint64_t *nbr_fw;  /* fluid -> wall, uint64[rows][2][n_fluid] */
     uint64_t *nbr_wf;  /* wall -> fluid, uint64[rows][2][n_wall] */
@@ -160,7 +167,8 @@ typedef struct sph_buffers {
 int sph_configure(sph_desc *desc);
 
 /* Bytes of scratch the calls need for n_fluid fluid and n_wall wall
- * particles (cell counts, sort keys and permutation, reduction partials). */
+ * particles (cell counts, sort keys and permutation, reduction partials,
+ * the sigma handed from the momentum sweep to the next density update). */
 size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
 
 /* Loads the initial state and prepares the run (Sec. 3: the data is copied
@@ -190,7 +198,9 @@ int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
  * reinitialised density of Eq. (17) with rho* the current density, then
  * the half kick of Eq. (19) with the stored dv/dt and the drift of Eq. (20).
  * Writes the new density and the half-step velocity in place (current
- * copies) and the drifted positions to key[1], off[1], pid[1]. */
+ * copies) and the drifted positions to key[1], off[1], pid[1].  When
+ * sigma_ready is set, sigma comes from the momentum sweep at these
+ * positions (the same pairs summed in the same order, so the same bits). */
 int sph_density(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Wall dummy pressure by force balance with the fluid, Eq. (12), for every
@@ -209,6 +219,8 @@ int sph_wall_bc(const sph_desc *desc, sph_buffers *buf, void *stream);
  *   Eq. (11) (walls), the viscous term, the penalty force of Eqs. (13)-(15)
  *   if penalty_all, and g; stores it in acc and, unless SPH_NO_KICK, the
  *   velocity of Eq. (22) into the other velocity copy; swaps sel_vel.
+ *   The same sweep sums sigma_i of Eq. (4) for the next density update
+ *   into the scratch and sets sigma_ready.
  * Exactly one of the two may be given per call. */
 int sph_forces(const sph_desc *desc, sph_buffers *buf, unsigned which, void *stream);
 

@@ -49,7 +49,7 @@ class Buffers(C.Structure):
         ("nrm", C.c_void_p), ("fstart", C.c_void_p), ("wstart", C.c_void_p),
         ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t),
         ("status", C.c_void_p), ("diag", C.c_void_p), ("sigma_out", C.c_void_p),
-        ("probe", C.c_void_p), ("n_probe", C.c_int32), ("reserved", C.c_int32),
+        ("probe", C.c_void_p), ("n_probe", C.c_int32), ("sigma_ready", C.c_int32),
         ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
         ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p),
     ]

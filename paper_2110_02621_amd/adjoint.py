@@ -79,6 +79,7 @@ def load_state(S, st):
         c[k].copy_(st[k])
     for k in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
         S.t[k].copy_(st[k])
+    S.buf.sigma_ready = 0  # the stored sigma belongs to the overwritten state
 
 
 MASKS = ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf")

@@ -159,6 +159,7 @@ __device__ __forceinline__ void for_rows(const Par<T>& P, const int32_t* __restr
             R.jp = start[row + c[0] + 1];
             R.j0 = left ? R.base : R.jm;
             R.j1 = right ? start[row + c[0] + 2] : R.jp;
+            if (R.j0 >= R.j1) continue;  // no candidates: no mask word is written or read
             R.r = stencil_row<D>(y - c[1], z - c[2]);
             R.cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
             g(R, T(y - c[1]) * P.L, sz);
@@ -192,6 +193,8 @@ __device__ __forceinline__ void for_neighbours(const Par<T>& P, const int32_t* _
 // row's full 3-cell index range: bit b of word w marks candidate
 // base + 64 w + b as a pair.  count[q] is the number of pairs, or -1 when a
 // row had more than 128 candidates (that query walks the cells instead).
+// Rows without candidates, and the second word of rows of at most 64
+// candidates, are neither written nor read.
 // Storage is interleaved across queries: a wave reads or writes one word
 // of 64 queries in one coalesced access.
 struct NbrMask {
@@ -224,7 +227,7 @@ __device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __rest
             }
         }
         mask[(int64_t)(R.r * kMaskWords + 0) * n + i] = m0;
-        mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
+        if (R.j1 - R.base > 64) mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
     });
     return over ? -1 : count;
 }
@@ -238,8 +241,10 @@ __device__ __forceinline__ void for_mask(const Par<T>& P, const int32_t* __restr
                                          const uint64_t* __restrict__ mask, int64_t n, int64_t i,
                                          F&& f) {
     for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
-        const uint64_t m[kMaskWords] = {mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
-                                        mask[(int64_t)(R.r * kMaskWords + 1) * n + i]};
+        // the second word exists only for rows of more than 64 candidates
+        const uint64_t m[kMaskWords] = {
+            mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
+            R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull};
 #pragma unroll
         for (int w = 0; w < kMaskWords; ++w) {
             uint64_t bits = m[w];

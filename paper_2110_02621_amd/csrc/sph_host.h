@@ -98,6 +98,7 @@ struct Scratch {
     int32_t* wkey0;   // n_wall, unsorted wall keys (init only)
     void* woff0;      // dim * n_wall T, unsorted wall offsets (init only)
     double* part;     // diag partials
+    void* sig;        // n_fluid T: sigma summed by the last momentum sweep
     size_t bytes;
 };
 
@@ -122,6 +123,7 @@ inline Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
     s.wkey0 = (int32_t*)take(sizeof(int32_t) * (size_t)nw);
     s.woff0 = take(ts * (size_t)d->dim * (size_t)nw);
     s.part = (double*)take(sizeof(double) * kDiagVals * (size_t)ndiag);
+    s.sig = take(ts * (size_t)nf);
     s.bytes = o;
     return s;
 }

@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(kBlock)
               const int32_t* __restrict__ wstart, T* __restrict__ vel, T* __restrict__ drho,
               const T* __restrict__ acc, int32_t* __restrict__ key_out,
               int32_t* __restrict__ pid_out, T* __restrict__ off_out, T* __restrict__ sigma_out,
-              uint32_t* __restrict__ status) {
+              const T* __restrict__ sigma_in, uint32_t* __restrict__ status) {
     const int64_t i = global_index();
     if (i >= nf) return;
     const T* o0 = off;
@@ -376,9 +376,13 @@ __global__ void __launch_bounds__(kBlock)
     cell_of(P, key[i], c);
     const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
     T s = T(0), comp = T(0);
-    auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, root(r2))); };
-    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, addW);
-    if (nw > 0) visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
+    if (sigma_in) {
+        s = sigma_in[i];  // summed by the momentum sweep over the same pairs, in the same order
+    } else {
+        auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, root(r2))); };
+        visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, addW);
+        if (nw > 0) visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
+    }
     if (sigma_out) sigma_out[i] = s;
     // Eq. (17) in deviations from rho0: rho_s - rho0 = rho0 (sigma - sigma0)/sigma0.
     const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
@@ -535,7 +539,7 @@ __global__ void __launch_bounds__(kBlock)
                const T* __restrict__ vel, const T* __restrict__ drho,
                const T* __restrict__ woff, const int32_t* __restrict__ wstart,
                const T* __restrict__ pw, const T* __restrict__ nrm, T* __restrict__ acc,
-               T* __restrict__ vel_out, int kick) {
+               T* __restrict__ vel_out, T* __restrict__ sigma_next, int kick) {
     const int64_t i = global_index();
     if (i >= nf) return;
     const T* o0 = off;
@@ -550,7 +554,11 @@ __global__ void __launch_bounds__(kBlock)
     const T p_i = P.c2 * dri;
     const T inv_rho_i = T(1) / rho_i;
     T A[3] = {0, 0, 0};
+    // sigma of these positions, the next density update's sum (Eq. (4)):
+    // every visited pair, self included, fluid then walls, as k_density sums it
+    T s = T(0), comp = T(0);
     visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2, uint32_t) {
+        kahan_add(s, comp, wendland_W(P, root(r2)));
         if (!(r2 > T(0))) return;
         const T rinv = rsq(r2);
         const T r = r2 * rinv;
@@ -578,6 +586,7 @@ __global__ void __launch_bounds__(kBlock)
     if (nw > 0)
         visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
                              [&](int w, const T d[3], T r2, uint32_t) {
+                                 kahan_add(s, comp, wendland_W(P, root(r2)));
                                  if (!(r2 > T(0))) return;
                                  const T r = root(r2);
                                  const T F = wendland_F(P, r);
@@ -614,6 +623,7 @@ __global__ void __launch_bounds__(kBlock)
         acc[k * nf + i] = a;
         if (kick) vel_out[k * nf + i] = vi[k] + P.half_dt * a;
     }
+    sigma_next[i] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -876,6 +886,7 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     }
     b->sel_vel = 1 - b->sel_vel;
     b->sel_rho = 1 - b->sel_rho;
+    b->sigma_ready = 0;
     if (b->nbr_ff) {
         const Par<T> P = make_par<T>(d);
         if (n > 0) {
@@ -897,14 +908,17 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
 template <typename T, int D>
 int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
+    const bool ready = b->sigma_ready != 0;
+    b->sigma_ready = 0;  // the drift moves the positions it was summed at
     if (nf == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
+    const Scratch s = layout(d, nf, nw, b->scratch);
     hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, mask_ff(b),
                        mask_fw(b), nf, nw,
                        b->key[0], b->pid[0], (const T*)b->off[0], b->fstart, (const T*)b->woff,
                        b->wstart, (T*)b->vel[b->sel_vel], (T*)b->rho[b->sel_rho],
                        (const T*)b->acc, b->key[1], b->pid[1], (T*)b->off[1], (T*)b->sigma_out,
-                       b->status);
+                       ready ? (const T*)s.sig : nullptr, b->status);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
 }
@@ -944,15 +958,17 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     } else {
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
         if (nf > 0) {
+            const Scratch s = layout(d, nf, nw, b->scratch);
             hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
                                mask_ff(b), mask_fw(b), nf, nw,
                                b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
                                (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
                                (const T*)b->pw, (const T*)b->nrm, (T*)b->acc,
-                               (T*)b->vel[1 - sv], kick);
+                               (T*)b->vel[1 - sv], (T*)s.sig, kick);
             SPH_LAUNCH_CHECK();
         }
         if (kick) b->sel_vel = 1 - sv;
+        b->sigma_ready = 1;
     }
     return SPH_OK;
 }
@@ -989,6 +1005,7 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
     // current copies, then the sort brings everything to copy 0.
     b->sel_vel = 0;
     b->sel_rho = 0;
+    b->sigma_ready = 0;
     if (nf > 0) {
         hipLaunchKernelGGL((k_to_cells<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, fpos, nf, G,
                            b->key[1], (T*)b->off[1], b->status);

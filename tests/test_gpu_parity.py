@@ -398,3 +398,25 @@ def test_lists_and_cell_walk_agree_bitwise(solver_mod, name, prec):
     nfl = np.empty_like(raw["cnt_ff"])
     nfl[raw["pid"][0]] = raw["cnt_ff"] + raw["cnt_fw"]
     assert np.array_equal(cnt, nfl)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["box3d", "dam3d", "dam2d"])
+def test_sigma_from_momentum_sweep_is_bitwise_the_gathered_sum(solver_mod, name, prec):
+    # The momentum sweep sums sigma at the positions the next density update
+    # starts from; the update must give the same bits as its own neighbour sum.
+    from paper_2110_02621_amd import adjoint
+    sc = SMALL[name]()
+    S = solver_mod.Solver(sc, prec, keep_sigma=True)
+    S.step(5)
+    assert S.buf.sigma_ready == 1
+    st = adjoint.save_state(S)
+    S.density()                      # sigma handed over by the momentum sweep
+    fused = S.raw()
+    adjoint.load_state(S, st)        # clears sigma_ready: this density sums itself
+    assert S.buf.sigma_ready == 0
+    S.density()
+    gathered = S.raw()
+    assert np.array_equal(fused["sigma"], gathered["sigma"])
+    for k in ("key", "pid", "off", "vel", "rho"):
+        assert np.array_equal(fused[k], gathered[k]), k
