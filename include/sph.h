@@ -168,7 +168,13 @@ int sph_configure(sph_desc *desc);
 
 /* Bytes of scratch the calls need for n_fluid fluid and n_wall wall
  * particles (cell counts, sort keys and permutation, reduction partials,
- * the sigma handed from the momentum sweep to the next density update). */
+ * the sigma handed from the momentum sweep to the next density update, and
+ * packed copies of the sorted state that the sweeps gather from: offset
+ * with density and velocity per fluid particle, offset with p_w and the
+ * normal per wall particle, 4 T each).  Every call keeps the packed copies
+ * equal to the state it leaves; a caller that overwrites state arrays
+ * itself must call sph_build_cells (or sph_init) before the next
+ * sph_wall_bc or sph_forces. */
 size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
 
 /* Loads the initial state and prepares the run (Sec. 3: the data is copied

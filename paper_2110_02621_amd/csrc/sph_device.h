@@ -68,6 +68,22 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
+// Element j of a device array through a 32-bit byte offset from the array's
+// (wave-uniform) base, so the load takes the scalar-base addressing form and
+// needs no 64-bit address arithmetic per lane.  Every array here has fewer
+// than 2^26 elements.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* __restrict__ p, int j) {
+    return *(const T*)((const char*)p + (uint32_t)j * (uint32_t)sizeof(T));
+}
+
+// x shift of candidate j of a row: -L left of the query's cell [jm, jp),
+// 0 inside, +L right of it (the same values as T(ix) * L).
+template <typename T>
+__device__ __forceinline__ T row_shift(int j, int jm, int jp, T L) {
+    return j < jm ? -L : (j < jp ? T(0) : L);
+}
+
 // Relative vector r_i - r_j from cell + offset: with s = c_j - c_i per axis,
 // d = (o_i - o_j) - s L, every operation rounded on its own (no fused
 // multiply-add), and r^2 = (d0 d0 + d1 d1) + d2 d2.  The pair test r^2 < rc2
@@ -167,25 +183,69 @@ __device__ __forceinline__ void for_rows(const Par<T>& P, const int32_t* __restr
     }
 }
 
+// Packed per-particle record: three components and one extra value in one
+// 16-byte (FP32) or 32-byte (FP64) load.  The sweeps gather neighbour data
+// through these records: the texture addresser handles a gather by lanes,
+// so one record load costs what one scalar load does and brings four.
+template <typename T>
+struct alignas(4 * sizeof(T)) Rec {
+    T x, y, z, w;
+};
+
+template <typename T>
+__device__ __forceinline__ Rec<T> ld4(const Rec<T>* __restrict__ p, int j) {
+    return *(const Rec<T>*)((const char*)p + (uint32_t)j * (uint32_t)sizeof(Rec<T>));
+}
+
+// Neighbour position sources: separate component arrays (w = 0), or
+// packed records (x, y, z = offset; w = the value stored with it).
+template <typename T, int D>
+struct SoaSrc {
+    const T *x, *y, *z;
+    __device__ __forceinline__ Rec<T> operator()(int j) const {
+        Rec<T> q;
+        q.x = ldg(x, j);
+        q.y = ldg(y, j);
+        q.z = D == 3 ? ldg(z, j) : T(0);
+        q.w = T(0);
+        return q;
+    }
+};
+
+template <typename T>
+struct PackSrc {
+    const Rec<T>* p;
+    __device__ __forceinline__ Rec<T> operator()(int j) const { return ld4(p, j); }
+};
+
 // Visit every particle j of a cell-sorted set with |r_i - r_j|^2 < rc2,
 // for a query point in cell c with offset oi.  The x-neighbours of a cell
 // are adjacent in key order, so each (y, z) row of 3 cells is one
 // contiguous index range; the cell of j inside the row follows from the
-// row's cell starts.  f(j, d, r2, code) receives d = r_i - r_j and the
-// shift code of the pair.  Pairs come row by row in ascending j.
+// row's cell starts.  f(j, d, r2, code, q) receives d = r_i - r_j, the
+// shift code of the pair and j's record from the source.  Pairs come row
+// by row in ascending j.
+template <typename T, int D, typename S, typename F>
+__device__ __forceinline__ void walk_src(const Par<T>& P, const int32_t* __restrict__ start, const S& src,
+                                         const int c[3], const T oi[3], F&& f) {
+    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
+        for (int j = R.j0; j < R.j1; ++j) {
+            const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+            const Rec<T> q = src(j);
+            T d[3];
+            const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+            if (r2 < P.rc2) f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q);
+        }
+    });
+}
+
 template <typename T, int D, typename F>
 __device__ __forceinline__ void for_neighbours(const Par<T>& P, const int32_t* __restrict__ start,
                                                const T* __restrict__ o0, const T* __restrict__ o1,
                                                const T* __restrict__ o2, const int c[3],
                                                const T oi[3], F&& f) {
-    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
-        for (int j = R.j0; j < R.j1; ++j) {
-            const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
-            T d[3];
-            const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
-            if (r2 < P.rc2) f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits));
-        }
-    });
+    walk_src<T, D>(P, start, SoaSrc<T, D>{o0, o1, o2}, c, oi,
+                   [&](int j, const T* d, T r2, uint32_t code, const Rec<T>&) { f(j, d, r2, code); });
 }
 
 // Neighbour masks of one set: for query q and stencil row r, the words
@@ -205,20 +265,19 @@ struct NbrMask {
 
 // Build the masks of query i (rows kept by the walk only).  Returns the
 // pair count, or -1 on a row with more than 128 candidates.
-template <typename T, int D>
-__device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __restrict__ start,
-                                          const T* __restrict__ o0, const T* __restrict__ o1,
-                                          const T* __restrict__ o2, const int c[3], const T oi[3],
-                                          uint64_t* __restrict__ mask, int64_t n, int64_t i) {
+template <typename T, int D, typename S>
+__device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __restrict__ start, const S& src,
+                                          const int c[3], const T oi[3], uint64_t* __restrict__ mask,
+                                          int64_t n, int64_t i) {
     int count = 0;
     bool over = false;
     for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
         uint64_t m0 = 0, m1 = 0;
         if (R.j1 - R.base > 64 * kMaskWords) over = true;
         for (int j = R.j0; j < R.j1; ++j) {
-            const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+            const Rec<T> q = src(j);
             T d[3];
-            const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
+            const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
             if (r2 < P.rc2) {
                 const int b = j - R.base;
                 if (b < 64) m0 |= 1ull << b;
@@ -233,13 +292,13 @@ __device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __rest
 }
 
 // Visit the pairs recorded in the masks of query i: same rows and the
-// same ascending order as the walk, so sums are bit-identical to it.
-template <typename T, int D, typename F>
-__device__ __forceinline__ void for_mask(const Par<T>& P, const int32_t* __restrict__ start,
-                                         const T* __restrict__ o0, const T* __restrict__ o1,
-                                         const T* __restrict__ o2, const int c[3], const T oi[3],
-                                         const uint64_t* __restrict__ mask, int64_t n, int64_t i,
-                                         F&& f) {
+// same ascending order as the walk, so sums are bit-identical to it.  All
+// lanes of a wave sweep one row at a time, so their gathers fall into the
+// same few cells.
+template <typename T, int D, typename S, typename F>
+__device__ __forceinline__ void mask_src(const Par<T>& P, const int32_t* __restrict__ start, const S& src,
+                                         const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
+                                         int64_t n, int64_t i, F&& f) {
     for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
         // the second word exists only for rows of more than 64 candidates
         const uint64_t m[kMaskWords] = {
@@ -252,26 +311,37 @@ __device__ __forceinline__ void for_mask(const Par<T>& P, const int32_t* __restr
                 const int j = R.base + 64 * w + __builtin_ctzll(bits);
                 bits &= bits - 1;
                 const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+                const Rec<T> q = src(j);
                 T d[3];
-                const T r2 = rel2<T, D>(oi, o0[j], o1[j], D == 3 ? o2[j] : T(0), T(ix) * P.L, sy, sz, d);
-                f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits));
+                const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+                f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q);
             }
         }
     });
 }
 
 // The neighbours of query i: from its masks when they exist and did not
-// overflow, else by walking the cells.
+// overflow, else by walking the cells.  visit4 hands each pair j's record
+// to f(j, d, r2, code, q); visit reads separate component arrays and calls
+// f(j, d, r2, code).
+template <typename T, int D, typename S, typename F>
+__device__ __forceinline__ void visit4(const Par<T>& P, const NbrMask& M, int64_t i,
+                                       const int32_t* __restrict__ start, const S& src, const int c[3],
+                                       const T oi[3], F&& f) {
+    if (M.mask && M.count[i] >= 0) {
+        mask_src<T, D>(P, start, src, c, oi, M.mask, M.n, i, f);
+        return;
+    }
+    walk_src<T, D>(P, start, src, c, oi, f);
+}
+
 template <typename T, int D, typename F>
 __device__ __forceinline__ void visit(const Par<T>& P, const NbrMask& M, int64_t i,
                                       const int32_t* __restrict__ start, const T* __restrict__ o0,
                                       const T* __restrict__ o1, const T* __restrict__ o2,
                                       const int c[3], const T oi[3], F&& f) {
-    if (M.mask && M.count[i] >= 0) {
-        for_mask<T, D>(P, start, o0, o1, o2, c, oi, M.mask, M.n, i, f);
-        return;
-    }
-    for_neighbours<T, D>(P, start, o0, o1, o2, c, oi, f);
+    visit4<T, D>(P, M, i, start, SoaSrc<T, D>{o0, o1, o2}, c, oi,
+                 [&](int j, const T* d, T r2, uint32_t code, const Rec<T>&) { f(j, d, r2, code); });
 }
 
 // Quintic Wendland C2 (kappa = 2) at r: q = r/h, t = 1 - q/2,

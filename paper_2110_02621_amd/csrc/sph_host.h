@@ -99,6 +99,14 @@ struct Scratch {
     void* woff0;      // dim * n_wall T, unsorted wall offsets (init only)
     double* part;     // diag partials
     void* sig;        // n_fluid T: sigma summed by the last momentum sweep
+    // packed copies of the sorted state that the sweeps gather from
+    // (Rec<T> = 4 T): pk[s] = (offset, rho[s] - rho0), vk[s] = (vel[s], 0)
+    // mirror the two density and velocity copies; wk = (wall offset, p_w),
+    // nk = (wall normal, 0)
+    void* pk[2];
+    void* vk[2];
+    void* wk;
+    void* nk;
     size_t bytes;
 };
 
@@ -124,6 +132,10 @@ inline Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
     s.woff0 = take(ts * (size_t)d->dim * (size_t)nw);
     s.part = (double*)take(sizeof(double) * kDiagVals * (size_t)ndiag);
     s.sig = take(ts * (size_t)nf);
+    for (int k = 0; k < 2; ++k) s.pk[k] = take(4 * ts * (size_t)nf);
+    for (int k = 0; k < 2; ++k) s.vk[k] = take(4 * ts * (size_t)nf);
+    s.wk = take(4 * ts * (size_t)nw);
+    s.nk = take(4 * ts * (size_t)nw);
     s.bytes = o;
     return s;
 }

@@ -199,18 +199,25 @@ __global__ void __launch_bounds__(kBlock)
                    const int32_t* __restrict__ pid_in, const T* __restrict__ off_in,
                    const T* __restrict__ vel_in, const T* __restrict__ rho_in,
                    int32_t* __restrict__ key_out, int32_t* __restrict__ pid_out,
-                   T* __restrict__ off_out, T* __restrict__ vel_out, T* __restrict__ rho_out) {
+                   T* __restrict__ off_out, T* __restrict__ vel_out, T* __restrict__ rho_out,
+                   Rec<T>* __restrict__ pk_out, Rec<T>* __restrict__ vk_out) {
     const int64_t i = global_index();
     if (i >= n) return;
     const int64_t s = perm[i];
     key_out[i] = key_in[s];
     pid_out[i] = pid_in[s];
-    rho_out[i] = rho_in[s];
+    const T r = rho_in[s];
+    rho_out[i] = r;
+    T o[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        off_out[k * n + i] = off_in[k * n + s];
-        vel_out[k * n + i] = vel_in[k * n + s];
+        o[k] = off_in[k * n + s];
+        v[k] = vel_in[k * n + s];
+        off_out[k * n + i] = o[k];
+        vel_out[k * n + i] = v[k];
     }
+    pk_out[i] = Rec<T>{o[0], o[1], o[2], r};
+    vk_out[i] = Rec<T>{v[0], v[1], v[2], T(0)};
 }
 
 template <typename T, int D>
@@ -227,6 +234,18 @@ __global__ void __launch_bounds__(kBlock)
     inv[s] = (int32_t)i;
 #pragma unroll
     for (int k = 0; k < D; ++k) off_out[k * n + i] = off_in[k * n + s];
+}
+
+// Packed wall records: offset with p_w (w filled by the wall pressure) and
+// the normal.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_pack_walls(int64_t nw, const T* __restrict__ woff, const T* __restrict__ nrm,
+                 Rec<T>* __restrict__ wk, Rec<T>* __restrict__ nk) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nw) return;
+    wk[w] = Rec<T>{woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0), T(0)};
+    nk[w] = Rec<T>{nrm[w], nrm[nw + w], D == 3 ? nrm[2 * nw + w] : T(0), T(0)};
 }
 
 // ---------------------------------------------------------------------------
@@ -318,6 +337,7 @@ __global__ void __launch_bounds__(kBlock)
 
 template <typename T>
 __device__ __forceinline__ void kahan_add(T& s, T& comp, T v) {
+#pragma clang fp contract(off)  // the same rounding wherever it is inlined
     if (std::is_same<T, float>::value) {
         const T y = v - comp;
         const T t = s + y;
@@ -366,7 +386,8 @@ __global__ void __launch_bounds__(kBlock)
               const int32_t* __restrict__ wstart, T* __restrict__ vel, T* __restrict__ drho,
               const T* __restrict__ acc, int32_t* __restrict__ key_out,
               int32_t* __restrict__ pid_out, T* __restrict__ off_out, T* __restrict__ sigma_out,
-              const T* __restrict__ sigma_in, uint32_t* __restrict__ status) {
+              const T* __restrict__ sigma_in, Rec<T>* __restrict__ pk, Rec<T>* __restrict__ vk,
+              uint32_t* __restrict__ status) {
     const int64_t i = global_index();
     if (i >= nf) return;
     const T* o0 = off;
@@ -388,15 +409,18 @@ __global__ void __launch_bounds__(kBlock)
     const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
     const T dstar = drho[i];
     const T excess = dstar - drs;
-    drho[i] = excess > T(0) ? drs + excess * P.rho0 / (P.rho0 + dstar) : drs;
+    const T dtil = excess > T(0) ? drs + excess * P.rho0 / (P.rho0 + dstar) : drs;
+    drho[i] = dtil;
     // Eqs. (19)-(20): half kick, drift, renormalise the cell.
     int cn[3] = {c[0], c[1], c[2]};
     const int nmax[3] = {P.nx, P.ny, P.nz};
     bool out = false;
+    T vh[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const T v = vel[k * nf + i] + P.half_dt * acc[k * nf + i];
         vel[k * nf + i] = v;
+        vh[k] = v;
         T o = oi[k] + P.dt * v;
         int ck = c[k] + renormalise(o, P.L, status);
         if (ck < 0) {
@@ -414,6 +438,9 @@ __global__ void __launch_bounds__(kBlock)
     if (out) atomicAdd(&status[SPH_STATUS_OUT_OF_GRID], 1u);
     key_out[i] = cn[0] + P.nx * (cn[1] + P.ny * cn[2]);
     pid_out[i] = pid[i];
+    // packed copies of the sorted state: same offsets, the new density and velocity
+    pk[i] = Rec<T>{oi[0], oi[1], oi[2], dtil};
+    vk[i] = Rec<T>{vh[0], vh[1], vh[2], T(0)};
 }
 
 // ---------------------------------------------------------------------------
@@ -423,19 +450,20 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_wall_bc(Par<T> P, NbrMask LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
-              const T* __restrict__ woff, const T* __restrict__ off,
-              const int32_t* __restrict__ fstart, const T* __restrict__ drho, T* __restrict__ pw) {
+              const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
+              Rec<T>* __restrict__ wk, T* __restrict__ pw) {
     const int64_t w = global_index();
     if (w >= nw) return;
     int c[3];
     cell_of(P, wkey[w], c);
-    const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
+    const Rec<T> me = wk[w];
+    const T ow[3] = {me.x, me.y, me.z};
     T sW = T(0), sP = T(0), sR[3] = {0, 0, 0};
     if (nf > 0)
-        visit<T, D>(P, LWF, w, fstart, off, off + nf, off + 2 * nf, c, ow,
-                             [&](int f, const T d[3], T r2, uint32_t) {
+        visit4<T, D>(P, LWF, w, fstart, PackSrc<T>{pk}, c, ow,
+                             [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
                                  const T W = wendland_W(P, root(r2));
-                                 const T dr = drho[f];
+                                 const T dr = q.w;
                                  sW += W;
                                  sP += P.c2 * dr * W;
                                  const T rW = (P.rho0 + dr) * W;
@@ -445,7 +473,9 @@ __global__ void __launch_bounds__(kBlock)
     T gR = T(0);
 #pragma unroll
     for (int k = 0; k < D; ++k) gR += P.gw[k] * sR[k];
-    pw[w] = sW > T(0) ? (sP + gR) / sW : T(0);
+    const T p = sW > T(0) ? (sP + gR) / sW : T(0);
+    pw[w] = p;
+    wk[w].w = p;
 }
 
 // Probe integral: diag[PROBE] += dt * mean(p_w over the probe walls).
@@ -479,49 +509,52 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_continuity(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
-                 const T* __restrict__ off, const int32_t* __restrict__ fstart,
-                 const T* __restrict__ vel, const T* __restrict__ drho,
-                 const T* __restrict__ woff, const int32_t* __restrict__ wstart,
-                 const T* __restrict__ pw, T* __restrict__ drho_out) {
+                 const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
+                 const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
+                 const Rec<T>* __restrict__ wk, T* __restrict__ drho_out, Rec<T>* __restrict__ pk_out) {
     const int64_t i = global_index();
     if (i >= nf) return;
-    const T* o0 = off;
-    const T* o1 = off + nf;
-    const T* o2 = off + 2 * nf;
     int c[3];
     cell_of(P, key[i], c);
-    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
-    const T vi[3] = {vel[i], vel[nf + i], D == 3 ? vel[2 * nf + i] : T(0)};
-    const T dri = drho[i];
+    const Rec<T> me = pk[i];
+    const Rec<T> mv = vk[i];
+    const T oi[3] = {me.x, me.y, me.z};
+    const T vi[3] = {mv.x, mv.y, mv.z};
+    const T dri = me.w;
     const T rho_i = P.rho0 + dri;
     T sum = T(0);
-    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2, uint32_t) {
+    visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi,
+                 [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q) {
         if (!(r2 > T(0))) return;
         const T r = root(r2);
         const T F = wendland_F(P, r);
-        const T drj = drho[j];
+        const T drj = q.w;
         const T rho_j = P.rho0 + drj;
+        const Rec<T> vj = ld4(vk, j);
+        const T vjk[3] = {vj.x, vj.y, vj.z};
         T vd = T(0);
 #pragma unroll
-        for (int k = 0; k < D; ++k) vd += (vi[k] - vel[k * nf + j]) * d[k];
-        const T q = rcp(rho_j * (rho_i + rho_j));
-        sum += F * q * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
+        for (int k = 0; k < D; ++k) vd += (vi[k] - vjk[k]) * d[k];
+        const T qq = rcp(rho_j * (rho_i + rho_j));
+        sum += F * qq * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
     });
     if (nw > 0)
-        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int w, const T d[3], T r2, uint32_t) {
-                                 if (!(r2 > T(0))) return;
-                                 const T r = root(r2);
-                                 const T F = wendland_F(P, r);
-                                 const T p_w = pw[w];
-                                 const T rho_w = P.rho0 + p_w * P.inv_c2;
-                                 T vd = T(0);
+        visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
+                     [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+                         if (!(r2 > T(0))) return;
+                         const T r = root(r2);
+                         const T F = wendland_F(P, r);
+                         const T p_w = q.w;
+                         const T rho_w = P.rho0 + p_w * P.inv_c2;
+                         T vd = T(0);
 #pragma unroll
-                                 for (int k = 0; k < D; ++k) vd += vi[k] * d[k];
-                                 const T q = rcp(rho_w * (rho_i + rho_w));
-                                 sum += F * q * (rho_w * vd + (P.c2 * dri - p_w) * r * P.cinv);
-                             });
-    drho_out[i] = dri + P.dt * (T(2) * rho_i * P.m * sum);
+                         for (int k = 0; k < D; ++k) vd += vi[k] * d[k];
+                         const T qq = rcp(rho_w * (rho_i + rho_w));
+                         sum += F * qq * (rho_w * vd + (P.c2 * dri - p_w) * r * P.cinv);
+                     });
+    const T dnew = dri + P.dt * (T(2) * rho_i * P.m * sum);
+    drho_out[i] = dnew;
+    pk_out[i] = Rec<T>{me.x, me.y, me.z, dnew};
 }
 
 // ---------------------------------------------------------------------------
@@ -535,21 +568,20 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_momentum(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
-               const T* __restrict__ off, const int32_t* __restrict__ fstart,
-               const T* __restrict__ vel, const T* __restrict__ drho,
-               const T* __restrict__ woff, const int32_t* __restrict__ wstart,
-               const T* __restrict__ pw, const T* __restrict__ nrm, T* __restrict__ acc,
-               T* __restrict__ vel_out, T* __restrict__ sigma_next, int kick) {
+               const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
+               const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
+               const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ nk, T* __restrict__ acc,
+               T* __restrict__ vel_out, Rec<T>* __restrict__ vk_out, T* __restrict__ sigma_next,
+               int kick) {
     const int64_t i = global_index();
     if (i >= nf) return;
-    const T* o0 = off;
-    const T* o1 = off + nf;
-    const T* o2 = off + 2 * nf;
     int c[3];
     cell_of(P, key[i], c);
-    const T oi[3] = {o0[i], o1[i], D == 3 ? o2[i] : T(0)};
-    const T vi[3] = {vel[i], vel[nf + i], D == 3 ? vel[2 * nf + i] : T(0)};
-    const T dri = drho[i];
+    const Rec<T> me = pk[i];
+    const Rec<T> mv = vk[i];
+    const T oi[3] = {me.x, me.y, me.z};
+    const T vi[3] = {mv.x, mv.y, mv.z};
+    const T dri = me.w;
     const T rho_i = P.rho0 + dri;
     const T p_i = P.c2 * dri;
     const T inv_rho_i = T(1) / rho_i;
@@ -557,72 +589,79 @@ __global__ void __launch_bounds__(kBlock)
     // sigma of these positions, the next density update's sum (Eq. (4)):
     // every visited pair, self included, fluid then walls, as k_density sums it
     T s = T(0), comp = T(0);
-    visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, [&](int j, const T d[3], T r2, uint32_t) {
+    visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi,
+                 [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q) {
         kahan_add(s, comp, wendland_W(P, root(r2)));
         if (!(r2 > T(0))) return;
         const T rinv = rsq(r2);
         const T r = r2 * rinv;
         const T F = wendland_F(P, r);
-        const T drj = drho[j];
+        const T drj = q.w;
         const T rho_j = P.rho0 + drj;
         const T p_j = P.c2 * drj;
+        const Rec<T> vj = ld4(vk, j);
+        const T vjk[3] = {vj.x, vj.y, vj.z};
         T dv[3];
         T vd = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            dv[k] = vi[k] - vel[k * nf + j];
+            dv[k] = vi[k] - vjk[k];
             vd += dv[k] * d[k];
         }
         const T jump = -vd * rinv;  // U_L - U_R
         const T beta = minv(T(3) * maxv(jump, T(0)), P.c);
         const T sum = rho_i + rho_j;
-        const T q = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
-        const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * q);
-        const T coef = P.m * F * (sum * q) * inv_rho_i;  // m F/(rho_i rho_j)
+        const T qq = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
+        const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * qq);
+        const T coef = P.m * F * (sum * qq) * inv_rho_i;  // m F/(rho_i rho_j)
         const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
 #pragma unroll
         for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
     });
     if (nw > 0)
-        visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
-                             [&](int w, const T d[3], T r2, uint32_t) {
-                                 kahan_add(s, comp, wendland_W(P, root(r2)));
-                                 if (!(r2 > T(0))) return;
-                                 const T r = root(r2);
-                                 const T F = wendland_F(P, r);
-                                 const T p_w = pw[w];
-                                 const T rho_w = P.rho0 + p_w * P.inv_c2;
-                                 const T sum = rho_i + rho_w;
-                                 const T q = rcp(rho_w * sum);
-                                 const T pstar = (rho_i * p_w + rho_w * p_i) * (rho_w * q);
-                                 const T coef = P.m * F * (sum * q) * inv_rho_i;
-                                 const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
-                                 T pen = T(0);
-                                 T nv[3] = {0, 0, 0};
-                                 if (P.penalty) {
-                                     T proj = T(0);
+        visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
+                     [&](int w, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+                         kahan_add(s, comp, wendland_W(P, root(r2)));
+                         if (!(r2 > T(0))) return;
+                         const T r = root(r2);
+                         const T F = wendland_F(P, r);
+                         const T p_w = q.w;
+                         const T rho_w = P.rho0 + p_w * P.inv_c2;
+                         const T sum = rho_i + rho_w;
+                         const T qq = rcp(rho_w * sum);
+                         const T pstar = (rho_i * p_w + rho_w * p_i) * (rho_w * qq);
+                         const T coef = P.m * F * (sum * qq) * inv_rho_i;
+                         const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
+                         T pen = T(0);
+                         T nv[3] = {0, 0, 0};
+                         if (P.penalty) {
+                             const Rec<T> nw4 = ld4(nk, w);
+                             nv[0] = nw4.x;
+                             nv[1] = nw4.y;
+                             nv[2] = D == 3 ? nw4.z : T(0);
+                             T proj = T(0);
 #pragma unroll
-                                     for (int k = 0; k < D; ++k) {
-                                         nv[k] = nrm[k * nw + w];
-                                         proj += d[k] * nv[k];
-                                     }
-                                     const T ap = absv(proj);
-                                     const T delta = P.two_over_dx * ap;
-                                     if (delta < T(1)) {
-                                         const T om = T(1) - delta;
-                                         pen = -T(2) * P.gamma_p * om * om * absv(p_i) * ap;
-                                     }
-                                 }
+                             for (int k = 0; k < D; ++k) proj += d[k] * nv[k];
+                             const T ap = absv(proj);
+                             const T delta = P.two_over_dx * ap;
+                             if (delta < T(1)) {
+                                 const T om = T(1) - delta;
+                                 pen = -T(2) * P.gamma_p * om * om * absv(p_i) * ap;
+                             }
+                         }
 #pragma unroll
-                                 for (int k = 0; k < D; ++k)
-                                     A[k] += coef * (visc * vi[k] - T(2) * pstar * d[k] + pen * nv[k]);
-                             });
+                         for (int k = 0; k < D; ++k)
+                             A[k] += coef * (visc * vi[k] - T(2) * pstar * d[k] + pen * nv[k]);
+                     });
+    T vn[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const T a = A[k] + P.g[k];
         acc[k * nf + i] = a;
-        if (kick) vel_out[k * nf + i] = vi[k] + P.half_dt * a;
+        vn[k] = vi[k] + P.half_dt * a;
+        if (kick) vel_out[k * nf + i] = vn[k];
     }
+    if (kick) vk_out[i] = Rec<T>{vn[0], vn[1], vn[2], T(0)};
     sigma_next[i] = s;
 }
 
@@ -637,19 +676,20 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_masks_fluid(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
-                  const T* __restrict__ off, const int32_t* __restrict__ fstart,
-                  const T* __restrict__ woff, const int32_t* __restrict__ wstart,
+                  const Rec<T>* __restrict__ pk, const int32_t* __restrict__ fstart,
+                  const Rec<T>* __restrict__ wk, const int32_t* __restrict__ wstart,
                   uint64_t* __restrict__ mf, int32_t* __restrict__ cf, uint64_t* __restrict__ mw,
                   int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
     const int64_t i = global_index();
     if (i >= nf) return;
     int c[3];
     cell_of(P, key[i], c);
-    const T oi[3] = {off[i], off[nf + i], D == 3 ? off[2 * nf + i] : T(0)};
-    const int n = build_mask<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, oi, mf, nf, i);
+    const Rec<T> me = pk[i];
+    const T oi[3] = {me.x, me.y, me.z};
+    const int n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, mf, nf, i);
     cf[i] = n;
     int m = 0;
-    if (nw > 0) m = build_mask<T, D>(P, wstart, woff, woff + nw, woff + 2 * nw, c, oi, mw, nf, i);
+    if (nw > 0) m = build_mask<T, D>(P, wstart, PackSrc<T>{wk}, c, oi, mw, nf, i);
     cw[i] = m;
     if (n < 0 || m < 0) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
 }
@@ -657,16 +697,17 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_masks_wall(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
-                 const T* __restrict__ woff, const T* __restrict__ off,
+                 const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ pk,
                  const int32_t* __restrict__ fstart, uint64_t* __restrict__ m,
                  int32_t* __restrict__ cnt, uint32_t* __restrict__ status) {
     const int64_t w = global_index();
     if (w >= nw) return;
     int c[3];
     cell_of(P, wkey[w], c);
-    const T ow[3] = {woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0)};
+    const Rec<T> me = wk[w];
+    const T ow[3] = {me.x, me.y, me.z};
     int n = 0;
-    if (nf > 0) n = build_mask<T, D>(P, fstart, off, off + nf, off + 2 * nf, c, ow, m, nw, w);
+    if (nf > 0) n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, ow, m, nw, w);
     cnt[w] = n;
     if (n < 0) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
 }
@@ -881,7 +922,8 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
         hipLaunchKernelGGL((k_gather_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, s.perm, n,
                            b->key[1], b->pid[1], (const T*)b->off[1], (const T*)b->vel[sv],
                            (const T*)b->rho[sr], b->key[0], b->pid[0], (T*)b->off[0],
-                           (T*)b->vel[1 - sv], (T*)b->rho[1 - sr]);
+                           (T*)b->vel[1 - sv], (T*)b->rho[1 - sr], (Rec<T>*)s.pk[1 - sr],
+                           (Rec<T>*)s.vk[1 - sv]);
         SPH_LAUNCH_CHECK();
     }
     b->sel_vel = 1 - b->sel_vel;
@@ -889,15 +931,16 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     b->sigma_ready = 0;
     if (b->nbr_ff) {
         const Par<T> P = make_par<T>(d);
+        const Rec<T>* pk = (const Rec<T>*)s.pk[b->sel_rho];
         if (n > 0) {
             hipLaunchKernelGGL((k_masks_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, b->n_wall,
-                               b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->woff, b->wstart,
+                               b->key[0], pk, b->fstart, (const Rec<T>*)s.wk, b->wstart,
                                b->nbr_ff, b->cnt_ff, b->nbr_fw, b->cnt_fw, b->status);
             SPH_LAUNCH_CHECK();
         }
         if (b->n_wall > 0) {
             hipLaunchKernelGGL((k_masks_wall<T, D>), dim3(grid_for(b->n_wall)), dim3(kBlock), 0, st, P, n,
-                               b->n_wall, b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
+                               b->n_wall, b->wkey, (const Rec<T>*)s.wk, pk, b->fstart,
                                b->nbr_wf, b->cnt_wf, b->status);
             SPH_LAUNCH_CHECK();
         }
@@ -918,7 +961,8 @@ int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
                        b->key[0], b->pid[0], (const T*)b->off[0], b->fstart, (const T*)b->woff,
                        b->wstart, (T*)b->vel[b->sel_vel], (T*)b->rho[b->sel_rho],
                        (const T*)b->acc, b->key[1], b->pid[1], (T*)b->off[1], (T*)b->sigma_out,
-                       ready ? (const T*)s.sig : nullptr, b->status);
+                       ready ? (const T*)s.sig : nullptr, (Rec<T>*)s.pk[b->sel_rho],
+                       (Rec<T>*)s.vk[b->sel_vel], b->status);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
 }
@@ -928,12 +972,11 @@ int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = tr
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nw == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
+    const Scratch s = layout(d, nf, nw, b->scratch);
     hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf, nw,
-                       b->wkey, (const T*)b->woff, (const T*)b->off[0], b->fstart,
-                       (const T*)b->rho[b->sel_rho], (T*)b->pw);
+                       b->wkey, b->fstart, (const Rec<T>*)s.pk[b->sel_rho], (Rec<T>*)s.wk, (T*)b->pw);
     SPH_LAUNCH_CHECK();
     if (probe && b->n_probe > 0) {
-        const Scratch s = layout(d, nf, nw, b->scratch);
         hipLaunchKernelGGL((k_probe<T>), dim3(1), dim3(kBlock), 0, st, (const T*)b->pw, s.winv, nw,
                            b->probe, b->n_probe, d->dt, b->diag);
         SPH_LAUNCH_CHECK();
@@ -946,25 +989,25 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     const Par<T> P = make_par<T>(d);
     const int sv = b->sel_vel, sr = b->sel_rho;
+    const Scratch s = layout(d, nf, nw, b->scratch);
+    const Rec<T>* wk = (const Rec<T>*)s.wk;
     if (which & SPH_CONTINUITY) {
         if (nf > 0) {
             hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
-                               (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
-                               (const T*)b->pw, (T*)b->rho[1 - sr]);
+                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->fstart,
+                               (const Rec<T>*)s.pk[sr], (const Rec<T>*)s.vk[sv], b->wstart, wk,
+                               (T*)b->rho[1 - sr], (Rec<T>*)s.pk[1 - sr]);
             SPH_LAUNCH_CHECK();
         }
         b->sel_rho = 1 - sr;
     } else {
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
         if (nf > 0) {
-            const Scratch s = layout(d, nf, nw, b->scratch);
             hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               mask_ff(b), mask_fw(b), nf, nw,
-                               b->key[0], (const T*)b->off[0], b->fstart, (const T*)b->vel[sv],
-                               (const T*)b->rho[sr], (const T*)b->woff, b->wstart,
-                               (const T*)b->pw, (const T*)b->nrm, (T*)b->acc,
-                               (T*)b->vel[1 - sv], (T*)s.sig, kick);
+                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->fstart,
+                               (const Rec<T>*)s.pk[sr], (const Rec<T>*)s.vk[sv], b->wstart, wk,
+                               (const Rec<T>*)s.nk, (T*)b->acc, (T*)b->vel[1 - sv],
+                               (Rec<T>*)s.vk[1 - sv], (T*)s.sig, kick);
             SPH_LAUNCH_CHECK();
         }
         if (kick) b->sel_vel = 1 - sv;
@@ -999,6 +1042,9 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
         SPH_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_normals<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, nw, b->wkey,
                            (const T*)b->woff, b->wstart, (T*)b->nrm);
+        SPH_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_pack_walls<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, nw,
+                           (const T*)b->woff, (const T*)b->nrm, (Rec<T>*)s.wk, (Rec<T>*)s.nk);
         SPH_LAUNCH_CHECK();
     }
     // fluid: cells of the initial positions into copy 1, state into the

@@ -4,9 +4,11 @@ theta = (mu, gamma_p, c0, H); J = sum_n dt mean(p_w over the probe).
   * FP64 GPU adjoint vs FP64 GPU central differences of the same forward:
     checks the backward kernels alone (tight bound).
   * FP32 GPU adjoint (FP64 accumulation) vs FP64 oracle central differences
-    with a relative step of 1e-4: the end-to-end check.  The viscosity's
-    share of J is ~1e-9 of J, below what a 1e-4 step resolves in FP64, so
-    mu takes a 1e-2 step (J is linear in mu to well below that noise).
+    with a relative step of 1e-4: the end-to-end check.  The viscous term
+    moves J by ~1e-7 of J, so a small step leaves the difference of the two
+    runs within FP64 rounding of J; mu takes a 1e-1 step instead (J depends
+    on mu through that term only, so its curvature in mu is of the order of
+    the square of that share and the step adds no visible truncation).
 Checkpointing (K < steps) must not change the result.
 """
 import numpy as np
@@ -18,7 +20,7 @@ from paper_2110_02621_amd import scenes
 pytestmark = pytest.mark.gpu
 
 NAMES = ("mu", "gamma_p", "c0", "H")
-STEP = (1e-2, 1e-4, 1e-4, 1e-4)  # relative central-difference steps
+STEP = (1e-1, 1e-4, 1e-4, 1e-4)  # relative central-difference steps
 
 
 @pytest.fixture(scope="module")
