@@ -47,6 +47,19 @@ SORT_BYTES_PARTICLE = 116
 SORT_BYTES_CELL = 24
 DENSITY_BYTES_PARTICLE = 88
 
+# HBM bytes per launch of the two pair sweeps on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000,
+# the factors a plain 1 GiB device copy gives): see
+# profiles/kernels_dam_break_3d_dx0.0025_8obstacles_hbm.md.  They describe the
+# kernel sources whose SHA-256 is recorded; once those change the traffic is
+# reported as null until the counters are taken again.
+TRAFFIC = {
+    "sources_sha256": "815b5c347caee60ced869349f8420cc3ed586fbde1e9c7da28301d9d52536b83",
+    "momentum": 1704.7e6 + 265.4e6,
+    "continuity": 1678.9e6 + 138.2e6,
+}
+KERNEL_SOURCES = ("sph_kernels.hip", "sph_device.h", "sph_host.h")
+
 PEAK_FP32 = 157.3e12      # MI355X published FP32 vector peak (packed FMA)
 PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop x 2.4 GHz, one FMA per lane per clock
 PEAK_HBM = 8.0e12
@@ -96,6 +109,19 @@ def timed_run(solver_mod, scene, precision, steps, warmup):
     stage_ms = {n: sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps
                 for j, n in enumerate(names)}
     return S, wall, stage_ms
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes of `kernel` per launch, or None when the
+    kernel sources differ from the ones the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_02621_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return TRAFFIC.get(kernel)
 
 
 def pair_counts(S):
@@ -156,7 +182,7 @@ def main():
     dom = max(("continuity", "momentum"), key=lambda k: stage[k])
     ach = flops[dom] / (stage[dom] * 1e-3)
     roofline = dict(bound="alu", achieved=round(ach / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                    frac=round(ach / PEAK_FP32, 4), traffic=None, kernel=dom)
+                    frac=round(ach / PEAK_FP32, 4), traffic=measured_traffic(dom), kernel=dom)
     del S
     torch.cuda.empty_cache()
 
