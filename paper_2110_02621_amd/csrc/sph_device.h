@@ -149,36 +149,47 @@ struct Row {
     uint32_t cyz;
 };
 
+// Row (y, z) of query (c, oi): false when the row is skipped (its y/z gap
+// alone reaches past the support, or no candidate is left after trimming
+// its left and right cells).  Contraction is off so that every kernel that
+// inlines this (the mask builder and all sweeps) takes the same decisions.
+template <typename T, int D>
+__device__ __forceinline__ bool row_of(const Par<T>& P, const int32_t* __restrict__ start, const int c[3],
+                                       const T oi[3], int y, int z, Row& R) {
+#pragma clang fp contract(off)
+    const T reach = P.rc2 * T(kSkipMargin);
+    const T gz = D == 3 ? gap(z - c[2], oi[2], P.L) : T(0);
+    const T gy = gap(y - c[1], oi[1], P.L);
+    const T g2 = gy * gy + gz * gz;
+    if (!(g2 < reach)) return false;
+    const T rx2 = reach - g2;
+    const T gl = oi[0], gr = P.L - oi[0];
+    const int row = P.nx * (y + P.ny * z);
+    const bool left = c[0] > 0 && gl * gl < rx2;
+    const bool right = c[0] < P.nx - 1 && gr * gr < rx2;
+    R.base = start[row + max(c[0] - 1, 0)];
+    R.jm = start[row + c[0]];
+    R.jp = start[row + c[0] + 1];
+    R.j0 = left ? R.base : R.jm;
+    R.j1 = right ? start[row + c[0] + 2] : R.jp;
+    if (R.j0 >= R.j1) return false;  // no candidates: no mask word is written or read
+    R.r = stencil_row<D>(y - c[1], z - c[2]);
+    R.cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
+    return true;
+}
+
 // Iterate the rows of query (c, oi); g(row, sy, sz) is called per row kept.
 template <typename T, int D, typename G>
 __device__ __forceinline__ void for_rows(const Par<T>& P, const int32_t* __restrict__ start,
                                          const int c[3], const T oi[3], G&& g) {
-    const T reach = P.rc2 * T(kSkipMargin);
     const int zlo = D == 3 ? max(c[2] - 1, 0) : 0;
     const int zhi = D == 3 ? min(c[2] + 1, P.nz - 1) : 0;
     const int ylo = max(c[1] - 1, 0), yhi = min(c[1] + 1, P.ny - 1);
-    const T gl = oi[0], gr = P.L - oi[0];
     for (int z = zlo; z <= zhi; ++z) {
-        const T sz = T(z - c[2]) * P.L;
-        const T gz = D == 3 ? gap(z - c[2], oi[2], P.L) : T(0);
         for (int y = ylo; y <= yhi; ++y) {
-            const T gy = gap(y - c[1], oi[1], P.L);
-            const T g2 = gy * gy + gz * gz;
-            if (!(g2 < reach)) continue;
-            const T rx2 = reach - g2;
-            const int row = P.nx * (y + P.ny * z);
-            const bool left = c[0] > 0 && gl * gl < rx2;
-            const bool right = c[0] < P.nx - 1 && gr * gr < rx2;
             Row R;
-            R.base = start[row + max(c[0] - 1, 0)];
-            R.jm = start[row + c[0]];
-            R.jp = start[row + c[0] + 1];
-            R.j0 = left ? R.base : R.jm;
-            R.j1 = right ? start[row + c[0] + 2] : R.jp;
-            if (R.j0 >= R.j1) continue;  // no candidates: no mask word is written or read
-            R.r = stencil_row<D>(y - c[1], z - c[2]);
-            R.cyz = shift_code(0, y - c[1], z - c[2]) & ~(3u << kIdxBits);
-            g(R, T(y - c[1]) * P.L, sz);
+            if (!row_of<T, D>(P, start, c, oi, y, z, R)) continue;
+            g(R, T(y - c[1]) * P.L, T(z - c[2]) * P.L);
         }
     }
 }
@@ -318,6 +329,145 @@ __device__ __forceinline__ void mask_src(const Par<T>& P, const int32_t* __restr
             }
         }
     });
+}
+
+// Barrier for data that the lanes of one wave exchange through LDS.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cells spanned by the wave whose first particle is ib (consecutive sorted
+// particles): when all of them lie in one (y, z) row of cells (one_row), the
+// candidates of each stencil row of every lane lie in one index range,
+// [start of cell cx0 - 1, end of cell cx1 + 1) of that row.
+struct WaveSpan {
+    bool one_row;
+    int cy, cz, cx0, cx1;
+};
+
+template <typename T>
+__device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __restrict__ key, int64_t ib,
+                                              int64_t n) {
+    const int64_t il = ib + 63 < n ? ib + 63 : n - 1;
+    const int k0 = key[ib], k1 = key[il];
+    const int r0 = k0 / P.nx, r1 = k1 / P.nx;
+    WaveSpan S;
+    S.one_row = r0 == r1;
+    S.cx0 = k0 - r0 * P.nx;
+    S.cx1 = k1 - r1 * P.nx;
+    S.cy = r0 % P.ny;
+    S.cz = r0 / P.ny;
+    return S;
+}
+
+// Masked sweep with LDS-staged neighbour rows, for a wave in one row of
+// cells (WaveSpan::one_row): per stencil row the wave loads the row's index
+// range once, coalesced, into LDS (positions sp, velocities sv; at most CAP
+// records, else the row is gathered from memory), and each lane reads its
+// masked neighbours from there.  Lanes with on = false only help staging.
+// Pairs come in the order of mask_src, so sums are bit-identical to it.
+// f(j, d, r2, code, q, u) gets j's position record q and velocity record u.
+template <typename T, int D, int CAP, typename F>
+__device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __restrict__ start,
+                                            const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
+                                            Rec<T>* sp, Rec<T>* sv, const WaveSpan& S, bool on,
+                                            const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
+                                            int64_t n, int64_t i, F&& f) {
+    const int lane = threadIdx.x & 63;
+    const int zlo = D == 3 ? max(S.cz - 1, 0) : 0;
+    const int zhi = D == 3 ? min(S.cz + 1, P.nz - 1) : 0;
+    const int ylo = max(S.cy - 1, 0), yhi = min(S.cy + 1, P.ny - 1);
+    for (int z = zlo; z <= zhi; ++z) {
+        for (int y = ylo; y <= yhi; ++y) {
+            Row R;
+            const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
+            if (!__any(kept)) continue;
+            const int row = P.nx * (y + P.ny * z);
+            const int ulo = start[row + max(S.cx0 - 1, 0)];
+            const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
+            const bool staged = uhi - ulo <= CAP;  // the same for every lane
+            if (staged) {
+                for (int k = lane; k < uhi - ulo; k += 64) {
+                    sp[k] = ld4(pk, ulo + k);
+                    sv[k] = ld4(vk, ulo + k);
+                }
+                wave_sync();
+            }
+            if (kept) {
+                const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
+                const uint64_t m[kMaskWords] = {
+                    mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
+                    R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull};
+#pragma unroll
+                for (int w = 0; w < kMaskWords; ++w) {
+                    uint64_t bits = m[w];
+                    while (bits) {
+                        const int j = R.base + 64 * w + __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+                        const Rec<T> q = staged ? sp[j - ulo] : ld4(pk, j);
+                        const Rec<T> u = staged ? sv[j - ulo] : ld4(vk, j);
+                        T d[3];
+                        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+                        f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
+                    }
+                }
+            }
+            if (staged) wave_sync();  // every lane is done with this row's records
+        }
+    }
+}
+
+// The mask builder with LDS-staged candidate rows (positions only), for a
+// wave in one row of cells; same results as build_mask.
+template <typename T, int D, int CAP>
+__device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t* __restrict__ start,
+                                                 const Rec<T>* __restrict__ pk, Rec<T>* sp, const WaveSpan& S,
+                                                 bool on, const int c[3], const T oi[3],
+                                                 uint64_t* __restrict__ mask, int64_t n, int64_t i) {
+    const int lane = threadIdx.x & 63;
+    const int zlo = D == 3 ? max(S.cz - 1, 0) : 0;
+    const int zhi = D == 3 ? min(S.cz + 1, P.nz - 1) : 0;
+    const int ylo = max(S.cy - 1, 0), yhi = min(S.cy + 1, P.ny - 1);
+    int count = 0;
+    bool over = false;
+    for (int z = zlo; z <= zhi; ++z) {
+        for (int y = ylo; y <= yhi; ++y) {
+            Row R;
+            const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
+            if (!__any(kept)) continue;
+            const int row = P.nx * (y + P.ny * z);
+            const int ulo = start[row + max(S.cx0 - 1, 0)];
+            const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
+            const bool staged = uhi - ulo <= CAP;
+            if (staged) {
+                for (int k = lane; k < uhi - ulo; k += 64) sp[k] = ld4(pk, ulo + k);
+                wave_sync();
+            }
+            if (kept) {
+                const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
+                uint64_t m0 = 0, m1 = 0;
+                if (R.j1 - R.base > 64 * kMaskWords) over = true;
+                for (int j = R.j0; j < R.j1; ++j) {
+                    const Rec<T> q = staged ? sp[j - ulo] : ld4(pk, j);
+                    T d[3];
+                    const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+                    if (r2 < P.rc2) {
+                        const int b = j - R.base;
+                        if (b < 64) m0 |= 1ull << b;
+                        else if (b < 128) m1 |= 1ull << (b - 64);
+                        ++count;
+                    }
+                }
+                mask[(int64_t)(R.r * kMaskWords + 0) * n + i] = m0;
+                if (R.j1 - R.base > 64) mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
+            }
+            if (staged) wave_sync();
+        }
+    }
+    return over ? -1 : count;
 }
 
 // The neighbours of query i: from its masks when they exist and did not

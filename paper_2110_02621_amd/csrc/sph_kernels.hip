@@ -335,6 +335,10 @@ __global__ void __launch_bounds__(kBlock)
 // drift Eq. (20) with cell renormalisation.
 // ---------------------------------------------------------------------------
 
+// Records per wave staged in LDS for one stencil row (a row of a wave that
+// spans about four cells holds ~100 particles; longer rows are gathered).
+constexpr int kStage = 160;
+
 template <typename T>
 __device__ __forceinline__ void kahan_add(T& s, T& comp, T v) {
 #pragma clang fp contract(off)  // the same rounding wherever it is inlined
@@ -512,8 +516,13 @@ __global__ void __launch_bounds__(kBlock)
                  const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                  const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                  const Rec<T>* __restrict__ wk, T* __restrict__ drho_out, Rec<T>* __restrict__ pk_out) {
-    const int64_t i = global_index();
-    if (i >= nf) return;
+    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
+    __shared__ Rec<T> stage_v[kBlock / 64][kStage];
+    const int64_t i0 = global_index();
+    const int64_t ib = i0 - (threadIdx.x & 63);
+    if (ib >= nf) return;  // the whole wave is past the end
+    const bool act = i0 < nf;
+    const int64_t i = act ? i0 : nf - 1;
     int c[3];
     cell_of(P, key[i], c);
     const Rec<T> me = pk[i];
@@ -523,21 +532,33 @@ __global__ void __launch_bounds__(kBlock)
     const T dri = me.w;
     const T rho_i = P.rho0 + dri;
     T sum = T(0);
-    visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi,
-                 [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+    auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
         if (!(r2 > T(0))) return;
         const T r = root(r2);
         const T F = wendland_F(P, r);
         const T drj = q.w;
         const T rho_j = P.rho0 + drj;
-        const Rec<T> vj = ld4(vk, j);
         const T vjk[3] = {vj.x, vj.y, vj.z};
         T vd = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) vd += (vi[k] - vjk[k]) * d[k];
         const T qq = rcp(rho_j * (rho_i + rho_j));
         sum += F * qq * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
-    });
+    };
+    auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
+        fluid(j, d, r2, code, q, ld4(vk, j));
+    };
+    const WaveSpan S = wave_span(P, key, ib, nf);
+    if (LF.mask && S.one_row) {
+        const bool m = act && LF.count[i] >= 0;
+        const int wv = threadIdx.x >> 6;
+        mask_staged<T, D, kStage>(P, fstart, pk, vk, stage_p[wv], stage_v[wv], S, m, c, oi, LF.mask, LF.n, i,
+                                  fluid);
+        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    } else if (act) {
+        visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    }
+    if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
@@ -573,8 +594,13 @@ __global__ void __launch_bounds__(kBlock)
                const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ nk, T* __restrict__ acc,
                T* __restrict__ vel_out, Rec<T>* __restrict__ vk_out, T* __restrict__ sigma_next,
                int kick) {
-    const int64_t i = global_index();
-    if (i >= nf) return;
+    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
+    __shared__ Rec<T> stage_v[kBlock / 64][kStage];
+    const int64_t i0 = global_index();
+    const int64_t ib = i0 - (threadIdx.x & 63);
+    if (ib >= nf) return;  // the whole wave is past the end
+    const bool act = i0 < nf;
+    const int64_t i = act ? i0 : nf - 1;
     int c[3];
     cell_of(P, key[i], c);
     const Rec<T> me = pk[i];
@@ -589,8 +615,7 @@ __global__ void __launch_bounds__(kBlock)
     // sigma of these positions, the next density update's sum (Eq. (4)):
     // every visited pair, self included, fluid then walls, as k_density sums it
     T s = T(0), comp = T(0);
-    visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi,
-                 [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+    auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
         kahan_add(s, comp, wendland_W(P, root(r2)));
         if (!(r2 > T(0))) return;
         const T rinv = rsq(r2);
@@ -599,7 +624,6 @@ __global__ void __launch_bounds__(kBlock)
         const T drj = q.w;
         const T rho_j = P.rho0 + drj;
         const T p_j = P.c2 * drj;
-        const Rec<T> vj = ld4(vk, j);
         const T vjk[3] = {vj.x, vj.y, vj.z};
         T dv[3];
         T vd = T(0);
@@ -617,7 +641,21 @@ __global__ void __launch_bounds__(kBlock)
         const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
 #pragma unroll
         for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
-    });
+    };
+    auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
+        fluid(j, d, r2, code, q, ld4(vk, j));
+    };
+    const WaveSpan S = wave_span(P, key, ib, nf);
+    if (LF.mask && S.one_row) {
+        const bool m = act && LF.count[i] >= 0;
+        const int wv = threadIdx.x >> 6;
+        mask_staged<T, D, kStage>(P, fstart, pk, vk, stage_p[wv], stage_v[wv], S, m, c, oi, LF.mask, LF.n, i,
+                                  fluid);
+        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    } else if (act) {
+        visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    }
+    if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int w, const T d[3], T r2, uint32_t, const Rec<T>& q) {
@@ -680,13 +718,23 @@ __global__ void __launch_bounds__(kBlock)
                   const Rec<T>* __restrict__ wk, const int32_t* __restrict__ wstart,
                   uint64_t* __restrict__ mf, int32_t* __restrict__ cf, uint64_t* __restrict__ mw,
                   int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
-    const int64_t i = global_index();
-    if (i >= nf) return;
+    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
+    const int64_t i0 = global_index();
+    const int64_t ib = i0 - (threadIdx.x & 63);
+    if (ib >= nf) return;  // the whole wave is past the end
+    const bool act = i0 < nf;
+    const int64_t i = act ? i0 : nf - 1;
     int c[3];
     cell_of(P, key[i], c);
     const Rec<T> me = pk[i];
     const T oi[3] = {me.x, me.y, me.z};
-    const int n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, mf, nf, i);
+    const WaveSpan S = wave_span(P, key, ib, nf);
+    int n = 0;
+    if (S.one_row)
+        n = build_mask_staged<T, D, kStage>(P, fstart, pk, stage_p[threadIdx.x >> 6], S, act, c, oi, mf, nf, i);
+    else if (act)
+        n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, mf, nf, i);
+    if (!act) return;
     cf[i] = n;
     int m = 0;
     if (nw > 0) m = build_mask<T, D>(P, wstart, PackSrc<T>{wk}, c, oi, mw, nf, i);
