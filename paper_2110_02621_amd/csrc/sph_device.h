@@ -331,6 +331,24 @@ __device__ __forceinline__ void mask_src(const Par<T>& P, const int32_t* __restr
     });
 }
 
+// Pointer into LDS (address space 3): reads through it compile to ds_read,
+// not to flat loads that would take the vector-memory path.
+#define SPH_LDS __attribute__((address_space(3)))
+
+template <typename T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ void lds_put(SPH_LDS Rec<T>* p, int k, const Rec<T>& v) {
+    *(SPH_LDS Vec4<T>*)((SPH_LDS char*)p + k * (int)sizeof(Rec<T>)) = Vec4<T>{v.x, v.y, v.z, v.w};
+}
+
+template <typename T>
+__device__ __forceinline__ Rec<T> lds_get(const SPH_LDS Rec<T>* p, int k) {
+    const Vec4<T> t = *(const SPH_LDS Vec4<T>*)((const SPH_LDS char*)p + k * (int)sizeof(Rec<T>));
+    return Rec<T>{t.x, t.y, t.z, t.w};
+}
+
 // Barrier for data that the lanes of one wave exchange through LDS.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -372,7 +390,7 @@ __device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __
 template <typename T, int D, int CAP, typename F>
 __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __restrict__ start,
                                             const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
-                                            Rec<T>* sp, Rec<T>* sv, const WaveSpan& S, bool on,
+                                            SPH_LDS Rec<T>* sp, SPH_LDS Rec<T>* sv, const WaveSpan& S, bool on,
                                             const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
                                             int64_t n, int64_t i, F&& f) {
     const int lane = threadIdx.x & 63;
@@ -390,8 +408,8 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
             const bool staged = uhi - ulo <= CAP;  // the same for every lane
             if (staged) {
                 for (int k = lane; k < uhi - ulo; k += 64) {
-                    sp[k] = ld4(pk, ulo + k);
-                    sv[k] = ld4(vk, ulo + k);
+                    lds_put(sp, k, ld4(pk, ulo + k));
+                    lds_put(sv, k, ld4(vk, ulo + k));
                 }
                 wave_sync();
             }
@@ -407,8 +425,8 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
                         const int j = R.base + 64 * w + __builtin_ctzll(bits);
                         bits &= bits - 1;
                         const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
-                        const Rec<T> q = staged ? sp[j - ulo] : ld4(pk, j);
-                        const Rec<T> u = staged ? sv[j - ulo] : ld4(vk, j);
+                        const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
+                        const Rec<T> u = staged ? lds_get(sv, j - ulo) : ld4(vk, j);
                         T d[3];
                         const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
                         f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
@@ -424,7 +442,7 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
 // wave in one row of cells; same results as build_mask.
 template <typename T, int D, int CAP>
 __device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t* __restrict__ start,
-                                                 const Rec<T>* __restrict__ pk, Rec<T>* sp, const WaveSpan& S,
+                                                 const Rec<T>* __restrict__ pk, SPH_LDS Rec<T>* sp, const WaveSpan& S,
                                                  bool on, const int c[3], const T oi[3],
                                                  uint64_t* __restrict__ mask, int64_t n, int64_t i) {
     const int lane = threadIdx.x & 63;
@@ -443,7 +461,7 @@ __device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t*
             const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
             const bool staged = uhi - ulo <= CAP;
             if (staged) {
-                for (int k = lane; k < uhi - ulo; k += 64) sp[k] = ld4(pk, ulo + k);
+                for (int k = lane; k < uhi - ulo; k += 64) lds_put(sp, k, ld4(pk, ulo + k));
                 wave_sync();
             }
             if (kept) {
@@ -451,7 +469,7 @@ __device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t*
                 uint64_t m0 = 0, m1 = 0;
                 if (R.j1 - R.base > 64 * kMaskWords) over = true;
                 for (int j = R.j0; j < R.j1; ++j) {
-                    const Rec<T> q = staged ? sp[j - ulo] : ld4(pk, j);
+                    const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
                     T d[3];
                     const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
                     if (r2 < P.rc2) {

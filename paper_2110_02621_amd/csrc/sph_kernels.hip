@@ -552,8 +552,8 @@ __global__ void __launch_bounds__(kBlock)
     if (LF.mask && S.one_row) {
         const bool m = act && LF.count[i] >= 0;
         const int wv = threadIdx.x >> 6;
-        mask_staged<T, D, kStage>(P, fstart, pk, vk, stage_p[wv], stage_v[wv], S, m, c, oi, LF.mask, LF.n, i,
-                                  fluid);
+        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage_p[wv], (SPH_LDS Rec<T>*)stage_v[wv],
+                                  S, m, c, oi, LF.mask, LF.n, i, fluid);
         if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
     } else if (act) {
         visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
@@ -649,8 +649,8 @@ __global__ void __launch_bounds__(kBlock)
     if (LF.mask && S.one_row) {
         const bool m = act && LF.count[i] >= 0;
         const int wv = threadIdx.x >> 6;
-        mask_staged<T, D, kStage>(P, fstart, pk, vk, stage_p[wv], stage_v[wv], S, m, c, oi, LF.mask, LF.n, i,
-                                  fluid);
+        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage_p[wv], (SPH_LDS Rec<T>*)stage_v[wv],
+                                  S, m, c, oi, LF.mask, LF.n, i, fluid);
         if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
     } else if (act) {
         visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
@@ -731,7 +731,8 @@ __global__ void __launch_bounds__(kBlock)
     const WaveSpan S = wave_span(P, key, ib, nf);
     int n = 0;
     if (S.one_row)
-        n = build_mask_staged<T, D, kStage>(P, fstart, pk, stage_p[threadIdx.x >> 6], S, act, c, oi, mf, nf, i);
+        n = build_mask_staged<T, D, kStage>(P, fstart, pk, (SPH_LDS Rec<T>*)stage_p[threadIdx.x >> 6], S, act,
+                                            c, oi, mf, nf, i);
     else if (act)
         n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, mf, nf, i);
     if (!act) return;
