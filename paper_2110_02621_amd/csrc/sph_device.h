@@ -366,10 +366,9 @@ struct WaveSpan {
 };
 
 template <typename T>
-__device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __restrict__ key, int64_t ib,
-                                              int64_t n) {
-    const int64_t il = ib + 63 < n ? ib + 63 : n - 1;
-    const int k0 = key[ib], k1 = key[il];
+__device__ __forceinline__ WaveSpan span_of(const Par<T>& P, const int32_t* __restrict__ key, int64_t first,
+                                            int64_t last) {
+    const int k0 = key[first], k1 = key[last];
     const int r0 = k0 / P.nx, r1 = k1 / P.nx;
     WaveSpan S;
     S.one_row = r0 == r1;
@@ -378,6 +377,12 @@ __device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __
     S.cy = r0 % P.ny;
     S.cz = r0 / P.ny;
     return S;
+}
+
+template <typename T>
+__device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __restrict__ key, int64_t ib,
+                                              int64_t n) {
+    return span_of(P, key, ib, ib + 63 < n ? ib + 63 : n - 1);
 }
 
 // Masked sweep with LDS-staged neighbour rows, for a wave in one row of
@@ -436,6 +441,91 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
             if (staged) wave_sync();  // every lane is done with this row's records
         }
     }
+}
+
+// Block-level form of mask_staged, for a block whose particles all lie in one
+// row of cells (S spans the block): the block stages each stencil row once
+// (up to CAP records) between block barriers, and every thread reads its
+// masked neighbours from there.  Every thread of the block must call it.
+template <typename T, int D, int CAP, typename F>
+__device__ __forceinline__ void mask_block(const Par<T>& P, const int32_t* __restrict__ start,
+                                           const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
+                                           SPH_LDS Rec<T>* sp, SPH_LDS Rec<T>* sv, const WaveSpan& S, bool on,
+                                           const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
+                                           int64_t n, int64_t i, F&& f) {
+    const int zlo = D == 3 ? max(S.cz - 1, 0) : 0;
+    const int zhi = D == 3 ? min(S.cz + 1, P.nz - 1) : 0;
+    const int ylo = max(S.cy - 1, 0), yhi = min(S.cy + 1, P.ny - 1);
+    for (int z = zlo; z <= zhi; ++z) {
+        for (int y = ylo; y <= yhi; ++y) {
+            Row R;
+            const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
+            if (!__syncthreads_or(kept)) continue;
+            const int row = P.nx * (y + P.ny * z);
+            const int ulo = start[row + max(S.cx0 - 1, 0)];
+            const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
+            const bool staged = uhi - ulo <= CAP;  // the same for every thread
+            if (staged) {
+                for (int k = threadIdx.x; k < uhi - ulo; k += blockDim.x) {
+                    lds_put(sp, k, ld4(pk, ulo + k));
+                    lds_put(sv, k, ld4(vk, ulo + k));
+                }
+                __syncthreads();
+            }
+            if (kept) {
+                const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
+                const uint64_t m[kMaskWords] = {
+                    mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
+                    R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull};
+#pragma unroll
+                for (int w = 0; w < kMaskWords; ++w) {
+                    uint64_t bits = m[w];
+                    while (bits) {
+                        const int j = R.base + 64 * w + __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+                        const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
+                        const Rec<T> u = staged ? lds_get(sv, j - ulo) : ld4(vk, j);
+                        T d[3];
+                        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+                        f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
+                    }
+                }
+            }
+            if (staged) __syncthreads();  // every thread is done with this row's records
+        }
+    }
+}
+
+// Lanes of a wave sweep a row of the stencil together, so a wave runs as
+// long as its busiest lane; how many neighbours a particle has in each row
+// depends on where it sits in its cell across the rows (y and z).  Threads
+// of a block in one row of cells therefore take the block's particles
+// grouped by that position (3 bands per axis), so the lanes of each wave
+// have similar per-row counts.  Returns the particle this thread sweeps.
+// Which thread takes which particle changes nothing in any result.
+template <typename T, int D>
+__device__ __forceinline__ int64_t regroup_block(const Par<T>& P, const Rec<T>* __restrict__ pk, int64_t blk0,
+                                                 int64_t nf, int* hist, int* perm) {
+    const int t = threadIdx.x;
+    const int64_t q = blk0 + t;
+    int b = 15;  // threads past the end go last
+    if (q < nf) {
+        const Rec<T> me = pk[q];
+        const T three = T(3) / P.L;
+        const int by = min((int)(me.y * three), 2);
+        const int bz = D == 3 ? min((int)(me.z * three), 2) : 0;
+        b = by + 3 * bz;
+    }
+    if (t < 16) hist[t] = 0;
+    __syncthreads();
+    const int slot = atomicAdd(&hist[b], 1);
+    __syncthreads();
+    int off = 0;
+    for (int k = 0; k < b; ++k) off += hist[k];
+    perm[off + slot] = t;
+    __syncthreads();
+    return blk0 + perm[t];
 }
 
 // The mask builder with LDS-staged candidate rows (positions only), for a

@@ -337,7 +337,42 @@ __global__ void __launch_bounds__(kBlock)
 
 // Records per wave staged in LDS for one stencil row (a row of a wave that
 // spans about four cells holds ~100 particles; longer rows are gathered).
+// A block staging for all its waves at once has kWaves * kStage records.
 constexpr int kStage = 160;
+constexpr int kWaves = kBlock / 64;
+
+// The fluid-fluid part of a pair sweep for particle i: block-staged when the
+// block lies in one row of cells (threads regrouped, see regroup_block),
+// else wave-staged when the wave does, else gathered from memory; lanes
+// whose masks overflowed walk the cells.  fluid(j, d, r2, code, q, u) takes
+// the position record q and velocity record u of j; fluid_g(j, d, r2, code,
+// q) the same with u loaded from memory.
+template <typename T, int D, typename F, typename G>
+__device__ __forceinline__ void fluid_sweep(const Par<T>& P, const NbrMask& LF, const int32_t* __restrict__ fstart,
+                                            const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
+                                            const int32_t* __restrict__ key, Rec<T>* stage, bool block_mode,
+                                            const WaveSpan& SB, bool act, int64_t ib, int64_t nf, int64_t i,
+                                            const int c[3], const T oi[3], F&& fluid, G&& fluid_g) {
+    if (block_mode) {
+        const bool m = act && LF.count[i] >= 0;
+        mask_block<T, D, kWaves * kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage,
+                                          (SPH_LDS Rec<T>*)(stage + kWaves * kStage), SB, m, c, oi, LF.mask,
+                                          LF.n, i, fluid);
+        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+        return;
+    }
+    const WaveSpan S = wave_span(P, key, ib, nf);
+    if (LF.mask && S.one_row) {
+        const bool m = act && LF.count[i] >= 0;
+        const int wv = threadIdx.x >> 6;
+        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)(stage + wv * kStage),
+                                  (SPH_LDS Rec<T>*)(stage + (kWaves + wv) * kStage), S, m, c, oi, LF.mask,
+                                  LF.n, i, fluid);
+        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    } else if (act) {
+        visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ void kahan_add(T& s, T& comp, T v) {
@@ -516,11 +551,16 @@ __global__ void __launch_bounds__(kBlock)
                  const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                  const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                  const Rec<T>* __restrict__ wk, T* __restrict__ drho_out, Rec<T>* __restrict__ pk_out) {
-    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
-    __shared__ Rec<T> stage_v[kBlock / 64][kStage];
-    const int64_t i0 = global_index();
+    __shared__ Rec<T> stage[2 * kWaves * kStage];
+    __shared__ int perm[kBlock];
+    __shared__ int hist[16];
+    const int64_t blk0 = (int64_t)logical_block() * kBlock;
+    if (blk0 >= nf) return;  // the whole block is past the end
+    const WaveSpan SB = span_of(P, key, blk0, (blk0 + kBlock < nf ? blk0 + kBlock : nf) - 1);
+    const bool block_mode = LF.mask && SB.one_row;
+    const int64_t i0 = block_mode ? regroup_block<T, D>(P, pk, blk0, nf, hist, perm) : blk0 + threadIdx.x;
     const int64_t ib = i0 - (threadIdx.x & 63);
-    if (ib >= nf) return;  // the whole wave is past the end
+    if (!block_mode && ib >= nf) return;  // the whole wave is past the end
     const bool act = i0 < nf;
     const int64_t i = act ? i0 : nf - 1;
     int c[3];
@@ -548,16 +588,7 @@ __global__ void __launch_bounds__(kBlock)
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
     };
-    const WaveSpan S = wave_span(P, key, ib, nf);
-    if (LF.mask && S.one_row) {
-        const bool m = act && LF.count[i] >= 0;
-        const int wv = threadIdx.x >> 6;
-        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage_p[wv], (SPH_LDS Rec<T>*)stage_v[wv],
-                                  S, m, c, oi, LF.mask, LF.n, i, fluid);
-        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
-    } else if (act) {
-        visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
-    }
+    fluid_sweep<T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid, fluid_g);
     if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
@@ -594,11 +625,16 @@ __global__ void __launch_bounds__(kBlock)
                const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ nk, T* __restrict__ acc,
                T* __restrict__ vel_out, Rec<T>* __restrict__ vk_out, T* __restrict__ sigma_next,
                int kick) {
-    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
-    __shared__ Rec<T> stage_v[kBlock / 64][kStage];
-    const int64_t i0 = global_index();
+    __shared__ Rec<T> stage[2 * kWaves * kStage];
+    __shared__ int perm[kBlock];
+    __shared__ int hist[16];
+    const int64_t blk0 = (int64_t)logical_block() * kBlock;
+    if (blk0 >= nf) return;  // the whole block is past the end
+    const WaveSpan SB = span_of(P, key, blk0, (blk0 + kBlock < nf ? blk0 + kBlock : nf) - 1);
+    const bool block_mode = LF.mask && SB.one_row;
+    const int64_t i0 = block_mode ? regroup_block<T, D>(P, pk, blk0, nf, hist, perm) : blk0 + threadIdx.x;
     const int64_t ib = i0 - (threadIdx.x & 63);
-    if (ib >= nf) return;  // the whole wave is past the end
+    if (!block_mode && ib >= nf) return;  // the whole wave is past the end
     const bool act = i0 < nf;
     const int64_t i = act ? i0 : nf - 1;
     int c[3];
@@ -645,16 +681,7 @@ __global__ void __launch_bounds__(kBlock)
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
     };
-    const WaveSpan S = wave_span(P, key, ib, nf);
-    if (LF.mask && S.one_row) {
-        const bool m = act && LF.count[i] >= 0;
-        const int wv = threadIdx.x >> 6;
-        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage_p[wv], (SPH_LDS Rec<T>*)stage_v[wv],
-                                  S, m, c, oi, LF.mask, LF.n, i, fluid);
-        if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
-    } else if (act) {
-        visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
-    }
+    fluid_sweep<T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid, fluid_g);
     if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
