@@ -2,7 +2,10 @@
 
 Flags: -O3, gfx950 only, packed FP32 instructions disabled
 (``-target-feature -packed-fp32-ops``); the float arithmetic is plain
-per-lane FP32.
+per-lane FP32.  ``-ffp-contract=on`` fuses a multiply and an add only
+within one source expression, so a formula rounds the same way in every
+kernel and code path that inlines it (the cell walk, the masked sweeps and
+their staged forms give bit-identical sums).
 """
 import os
 import subprocess
@@ -18,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 def command(out=LIB):
-    return [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    return [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
             "-Wall", "-Wno-unused-function", "-Wno-unused-lambda-capture",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-o", out] + SRC
