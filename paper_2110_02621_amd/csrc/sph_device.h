@@ -274,6 +274,37 @@ struct NbrMask {
     int64_t n;
 };
 
+// Pair bits of candidates [ja, jb) of row R into one mask word whose bit 0
+// is candidate wbase (jb - wbase <= 64): bit j - wbase is set when j is a
+// neighbour.  get(j) returns j's position record.
+template <typename T, int D, typename Get>
+__device__ __forceinline__ uint64_t row_bits(const Par<T>& P, const Row& R, int ja, int jb, int wbase,
+                                             const T oi[3], T sy, T sz, Get&& get) {
+    uint64_t m = 0;
+    if (ja >= jb) return m;
+    uint64_t bit = 1ull << (ja - wbase);
+    for (int j = ja; j < jb; ++j) {
+        const Rec<T> q = get(j);
+        T d[3];
+        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+        m |= r2 < P.rc2 ? bit : 0ull;
+        bit <<= 1;
+    }
+    return m;
+}
+
+// Both words of row R (candidates past base + 128 are not recorded; the
+// caller flags the row as overflowing).
+template <typename T, int D, typename Get>
+__device__ __forceinline__ void row_words(const Par<T>& P, const Row& R, const T oi[3], T sy, T sz, Get&& get,
+                                          uint64_t& m0, uint64_t& m1) {
+    const int split = R.base + 64;
+    m0 = row_bits<T, D>(P, R, R.j0, R.j1 < split ? R.j1 : split, R.base, oi, sy, sz, get);
+    m1 = R.j1 > split ? row_bits<T, D>(P, R, R.j0 > split ? R.j0 : split, R.j1 < split + 64 ? R.j1 : split + 64,
+                                       split, oi, sy, sz, get)
+                      : 0ull;
+}
+
 // Build the masks of query i (rows kept by the walk only).  Returns the
 // pair count, or -1 on a row with more than 128 candidates.
 template <typename T, int D, typename S>
@@ -283,19 +314,10 @@ __device__ __forceinline__ int build_mask(const Par<T>& P, const int32_t* __rest
     int count = 0;
     bool over = false;
     for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
-        uint64_t m0 = 0, m1 = 0;
+        uint64_t m0, m1;
         if (R.j1 - R.base > 64 * kMaskWords) over = true;
-        for (int j = R.j0; j < R.j1; ++j) {
-            const Rec<T> q = src(j);
-            T d[3];
-            const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
-            if (r2 < P.rc2) {
-                const int b = j - R.base;
-                if (b < 64) m0 |= 1ull << b;
-                else if (b < 128) m1 |= 1ull << (b - 64);
-                ++count;
-            }
-        }
+        row_words<T, D>(P, R, oi, sy, sz, src, m0, m1);
+        count += __builtin_popcountll(m0) + __builtin_popcountll(m1);
         mask[(int64_t)(R.r * kMaskWords + 0) * n + i] = m0;
         if (R.j1 - R.base > 64) mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
     });
@@ -556,19 +578,13 @@ __device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t*
             }
             if (kept) {
                 const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
-                uint64_t m0 = 0, m1 = 0;
+                uint64_t m0, m1;
                 if (R.j1 - R.base > 64 * kMaskWords) over = true;
-                for (int j = R.j0; j < R.j1; ++j) {
-                    const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
-                    T d[3];
-                    const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
-                    if (r2 < P.rc2) {
-                        const int b = j - R.base;
-                        if (b < 64) m0 |= 1ull << b;
-                        else if (b < 128) m1 |= 1ull << (b - 64);
-                        ++count;
-                    }
-                }
+                if (staged)
+                    row_words<T, D>(P, R, oi, sy, sz, [&](int j) { return lds_get(sp, j - ulo); }, m0, m1);
+                else
+                    row_words<T, D>(P, R, oi, sy, sz, [&](int j) { return ld4(pk, j); }, m0, m1);
+                count += __builtin_popcountll(m0) + __builtin_popcountll(m1);
                 mask[(int64_t)(R.r * kMaskWords + 0) * n + i] = m0;
                 if (R.j1 - R.base > 64) mask[(int64_t)(R.r * kMaskWords + 1) * n + i] = m1;
             }
