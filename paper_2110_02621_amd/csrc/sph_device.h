@@ -407,6 +407,49 @@ __device__ __forceinline__ WaveSpan wave_span(const Par<T>& P, const int32_t* __
     return span_of(P, key, ib, ib + 63 < n ? ib + 63 : n - 1);
 }
 
+// Visit the set bits of one mask word of row R (candidates wbase + bit) in
+// ascending order; get(j, q, u) loads j's position and velocity records.
+template <typename T, int D, typename Get, typename F>
+__device__ __forceinline__ void bits_loop(const Par<T>& P, const Row& R, int wbase, uint64_t bits,
+                                          const T oi[3], T sy, T sz, Get&& get, F&& f) {
+    while (bits) {
+        const int j = wbase + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
+        Rec<T> q, u;
+        get(j, q, u);
+        T d[3];
+        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+        f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
+    }
+}
+
+// A kept row of a masked sweep: its (one or two) words, with the records
+// from LDS when staged (at index j - ulo) or from memory.
+template <typename T, int D, typename F>
+__device__ __forceinline__ void masked_row(const Par<T>& P, const Row& R, const uint64_t* __restrict__ mask,
+                                           int64_t n, int64_t i, const T oi[3], T sy, T sz, bool staged,
+                                           const SPH_LDS Rec<T>* sp, const SPH_LDS Rec<T>* sv, int ulo,
+                                           const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk, F&& f) {
+    const uint64_t m0 = mask[(int64_t)(R.r * kMaskWords + 0) * n + i];
+    const uint64_t m1 = R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull;
+    if (staged) {
+        auto get = [&](int j, Rec<T>& q, Rec<T>& u) {
+            q = lds_get(sp, j - ulo);
+            u = lds_get(sv, j - ulo);
+        };
+        bits_loop<T, D>(P, R, R.base, m0, oi, sy, sz, get, f);
+        bits_loop<T, D>(P, R, R.base + 64, m1, oi, sy, sz, get, f);
+    } else {
+        auto get = [&](int j, Rec<T>& q, Rec<T>& u) {
+            q = ld4(pk, j);
+            u = ld4(vk, j);
+        };
+        bits_loop<T, D>(P, R, R.base, m0, oi, sy, sz, get, f);
+        bits_loop<T, D>(P, R, R.base + 64, m1, oi, sy, sz, get, f);
+    }
+}
+
 // Masked sweep with LDS-staged neighbour rows, for a wave in one row of
 // cells (WaveSpan::one_row): per stencil row the wave loads the row's index
 // range once, coalesced, into LDS (positions sp, velocities sv; at most CAP
@@ -440,26 +483,9 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
                 }
                 wave_sync();
             }
-            if (kept) {
-                const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
-                const uint64_t m[kMaskWords] = {
-                    mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
-                    R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull};
-#pragma unroll
-                for (int w = 0; w < kMaskWords; ++w) {
-                    uint64_t bits = m[w];
-                    while (bits) {
-                        const int j = R.base + 64 * w + __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
-                        const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
-                        const Rec<T> u = staged ? lds_get(sv, j - ulo) : ld4(vk, j);
-                        T d[3];
-                        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
-                        f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
-                    }
-                }
-            }
+            if (kept)
+                masked_row<T, D>(P, R, mask, n, i, oi, T(y - c[1]) * P.L, T(z - c[2]) * P.L, staged, sp, sv, ulo,
+                                 pk, vk, f);
             if (staged) wave_sync();  // every lane is done with this row's records
         }
     }
@@ -494,26 +520,9 @@ __device__ __forceinline__ void mask_block(const Par<T>& P, const int32_t* __res
                 }
                 __syncthreads();
             }
-            if (kept) {
-                const T sy = T(y - c[1]) * P.L, sz = T(z - c[2]) * P.L;
-                const uint64_t m[kMaskWords] = {
-                    mask[(int64_t)(R.r * kMaskWords + 0) * n + i],
-                    R.j1 - R.base > 64 ? mask[(int64_t)(R.r * kMaskWords + 1) * n + i] : 0ull};
-#pragma unroll
-                for (int w = 0; w < kMaskWords; ++w) {
-                    uint64_t bits = m[w];
-                    while (bits) {
-                        const int j = R.base + 64 * w + __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const int ix = j < R.jm ? -1 : (j < R.jp ? 0 : 1);
-                        const Rec<T> q = staged ? lds_get(sp, j - ulo) : ld4(pk, j);
-                        const Rec<T> u = staged ? lds_get(sv, j - ulo) : ld4(vk, j);
-                        T d[3];
-                        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
-                        f(j, d, r2, R.cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
-                    }
-                }
-            }
+            if (kept)
+                masked_row<T, D>(P, R, mask, n, i, oi, T(y - c[1]) * P.L, T(z - c[2]) * P.L, staged, sp, sv, ulo,
+                                 pk, vk, f);
             if (staged) __syncthreads();  // every thread is done with this row's records
         }
     }
