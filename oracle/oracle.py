@@ -31,6 +31,10 @@ class OrcParams(C.Structure):
         ("g", C.c_double * 3),
         ("a_wall", C.c_double * 3),
         ("sigma0", C.c_double),
+        ("two_phase", C.c_int32),
+        ("reserved", C.c_int32),
+        ("n_heavy", C.c_int64),
+        ("rho0_light", C.c_double),
     ]
 
 
@@ -99,8 +103,11 @@ def _check(rc, what):
 
 
 def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
-           a_wall=(0.0, 0.0, 0.0), sigma0=None, penalty_on=True) -> OrcParams:
-    """Parameter block.  sigma0 defaults to the lattice sum of Eq. (17)."""
+           a_wall=(0.0, 0.0, 0.0), sigma0=None, penalty_on=True, n_heavy=None,
+           rho0_light=None) -> OrcParams:
+    """Parameter block.  sigma0 defaults to the lattice sum of Eq. (17).
+    Two phases: fluid particles with index >= n_heavy have reference density
+    rho0_light (both given, or neither for a single phase)."""
     p = OrcParams()
     p.dim = int(dim)
     p.penalty_on = 1 if penalty_on else 0
@@ -109,12 +116,17 @@ def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
         p.g[k] = float(g[k]) if k < len(g) else 0.0
         p.a_wall[k] = float(a_wall[k]) if k < len(a_wall) else 0.0
     p.sigma0 = sigma0_lattice(dim, dx, h) if sigma0 is None else float(sigma0)
+    p.two_phase = 1 if rho0_light is not None else 0
+    p.n_heavy = int(n_heavy) if n_heavy is not None else 0
+    p.rho0_light = float(rho0_light) if rho0_light is not None else float(rho0)
     return p
 
 
 def params_from_scene(sc, **over) -> OrcParams:
     kw = dict(dim=sc.dim, dx=sc.dx, h=sc.h, rho0=sc.rho0, c=sc.c0, mu=sc.mu,
               gamma_p=sc.gamma_p, dt=sc.dt, g=tuple(sc.g), penalty_on=sc.penalty_all)
+    if getattr(sc, "rho0_light", None) is not None:
+        kw.update(n_heavy=sc.n_heavy, rho0_light=sc.rho0_light)
     kw.update(over)
     return params(**kw)
 

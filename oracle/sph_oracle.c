@@ -42,6 +42,19 @@
  *   schedule    per step: Eq. (17) reinit at r^n, Eq. (19) half kick,
  *               Eq. (20) drift, cell rebuild, Eq. (12) wall pressure,
  *               Eq. (9)+(21) density update, Eq. (10)+(22) second kick.
+ *   two phases  (two_phase = 1) fluid particles with index >= n_heavy are
+ *               the light phase (reference density rho0_light, the same
+ *               sound speed, Sec. 2.6): every particle carries its own
+ *               reference density and mass rho0_k dx^d; the light phase is
+ *               reinitialised by Eq. (18) and takes its density from the
+ *               number density after the drift instead of Eq. (9) (Secs.
+ *               2.1, 2.5, 2.6); Eq. (12) is divided by rho_f term by term
+ *               (Sec. 2.3); a wall dummy takes the reference density and
+ *               mass of the fluid particle it interacts with; the penalty
+ *               of Eq. (13) acts on light-phase particles (and on all when
+ *               penalty_on).  The Riemann solution of Eqs. (7)-(8) is used
+ *               as printed for pairs of either phase: its density weighting
+ *               carries the density ratio.
  */
 #define _DEFAULT_SOURCE
 #include <math.h>
@@ -74,6 +87,10 @@ typedef struct {
     double g[3];        /* body force */
     double a_wall[3];   /* wall acceleration in Eq. (12) */
     double sigma0;      /* reference number density of Eq. (17) */
+    int32_t two_phase;  /* 1: particles with index >= n_heavy are the light phase */
+    int32_t reserved;
+    int64_t n_heavy;    /* number of heavy-phase fluid particles (indices first) */
+    double rho0_light;  /* reference density of the light phase */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -352,13 +369,18 @@ void orc_riemann(double rhoL, double UL, double pL, double rhoR, double UR, doub
     out5[4] = o.beta;
 }
 
-/* Equation of state, Eq. (3). */
-static double eos_p(const orc_params *P, double rho) { return P->c * P->c * (rho - P->rho0); }
-/* Its inverse, used for the wall dummy density. */
-static double eos_rho(const orc_params *P, double p) { return P->rho0 + p / (P->c * P->c); }
-static double particle_mass(const orc_params *P)
+/* Phase of fluid particle i and its reference density rho0_k. */
+static int is_light(const orc_params *P, int64_t i) { return P->two_phase && i >= P->n_heavy; }
+static double ref_rho(const orc_params *P, int64_t i) { return is_light(P, i) ? P->rho0_light : P->rho0; }
+/* Equation of state, Eq. (3), for fluid particle i. */
+static double eos_p(const orc_params *P, int64_t i, double rho) { return P->c * P->c * (rho - ref_rho(P, i)); }
+/* Its inverse, for a wall dummy interacting with fluid particle i. */
+static double eos_rho(const orc_params *P, int64_t i, double p) { return ref_rho(P, i) + p / (P->c * P->c); }
+/* Particle mass rho0_k dx^d of fluid particle i (and of a wall dummy seen by i). */
+static double mass_of(const orc_params *P, int64_t i)
 {
-    return P->dim == 2 ? P->rho0 * P->dx * P->dx : P->rho0 * P->dx * P->dx * P->dx;
+    double v = P->dim == 2 ? P->dx * P->dx : P->dx * P->dx * P->dx;
+    return ref_rho(P, i) * v;
 }
 
 static double dot(int dim, const double *a, const double *b)
@@ -418,13 +440,19 @@ int orc_sigma(const orc_params *P, int64_t nf, const double *fx, int64_t nw, con
 }
 
 /* Density reinitialisation for free-surface flow, Eq. (17):
- * rho = rho0 sigma/sigma0 + max(0, rho* - rho0 sigma/sigma0) rho0/rho*. */
+ * rho = rho0 sigma/sigma0 + max(0, rho* - rho0 sigma/sigma0) rho0/rho*;
+ * for the light phase of a two-phase run the internal-flow form, Eq. (18):
+ * rho = rho0 sigma/sigma0. */
 void orc_reinit(const orc_params *P, int64_t n, const double *sigma, const double *rho_star,
                 double *rho)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double rs = P->rho0 * sigma[i] / P->sigma0;
-        rho[i] = rs + fmax(0.0, rho_star[i] - rs) * P->rho0 / rho_star[i];
+        double r0 = ref_rho(P, i);
+        double rs = r0 * sigma[i] / P->sigma0;
+        if (is_light(P, i))
+            rho[i] = rs;
+        else
+            rho[i] = rs + fmax(0.0, rho_star[i] - rs) * r0 / rho_star[i];
     }
 }
 
@@ -481,9 +509,17 @@ int orc_wall_pressure(const orc_params *P, int64_t nw, const double *wx, int64_t
                     r2 += rwf[k] * rwf[k];
                 }
                 double W = orc_W(dim, h, sqrt(r2));
-                sumW += W;
-                sumPW += eos_p(P, frho[f]) * W;
-                for (int k = 0; k < dim; ++k) sumRW[k] += frho[f] * rwf[k] * W;
+                double p_f = eos_p(P, f, frho[f]);
+                if (P->two_phase) {
+                    /* Eq. (12) divided by rho_f term by term (Sec. 2.3) */
+                    sumW += W / frho[f];
+                    sumPW += p_f / frho[f] * W;
+                    for (int k = 0; k < dim; ++k) sumRW[k] += rwf[k] * W;
+                } else {
+                    sumW += W;
+                    sumPW += p_f * W;
+                    for (int k = 0; k < dim; ++k) sumRW[k] += frho[f] * rwf[k] * W;
+                }
             }
             pw[a_q] = sumW > 0.0 ? (sumPW + dot(dim, gw, sumRW)) / sumW : 0.0;
         }
@@ -554,7 +590,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
                    int64_t nq, const int64_t *qidx, double *drhodt)
 {
     int dim = P->dim;
-    double h = P->h, rc2 = 4.0 * h * h, m = particle_mass(P);
+    double h = P->h, rc2 = 4.0 * h * h;
     cellset sf, sw;
     int rc = cs_build(&sf, dim, nf, fx, 2.0 * h);
     if (rc) return rc;
@@ -571,7 +607,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
         for (int64_t a_q = 0; a_q < nq; ++a_q) {
             int64_t i = qidx ? qidx[a_q] : a_q;
             const double *xi = fx + i * dim, *vi = fv + i * dim;
-            double rho_i = frho[i], p_i = eos_p(P, rho_i);
+            double rho_i = frho[i], p_i = eos_p(P, i, rho_i);
             double sum = 0.0;
             for (int set = 0; set < 2; ++set) {
                 const cellset *cs = set == 0 ? &sf : &sw;
@@ -596,14 +632,16 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
                         e[k] = -rij[k] / r;
                         gradW[k] = dW * rij[k] / r;
                     }
-                    double rho_j, p_j;
+                    double rho_j, p_j, m_j;
                     if (set == 0) {
                         for (int k = 0; k < dim; ++k) vj[k] = fv[j * dim + k];
                         rho_j = frho[j];
-                        p_j = eos_p(P, rho_j);
+                        p_j = eos_p(P, j, rho_j);
+                        m_j = mass_of(P, j);
                     } else {
                         p_j = pw[j];
-                        rho_j = eos_rho(P, p_j);
+                        rho_j = eos_rho(P, i, p_j);
+                        m_j = mass_of(P, i);
                     }
                     /* Eq. (7): left state from i, right state from j. */
                     double UL = dot(dim, vi, e), UR = dot(dim, vj, e);
@@ -614,7 +652,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
                                    rs.Ubar * e[k];
                         diff[k] = vi[k] - vstar[k];
                     }
-                    sum += m / rho_j * dot(dim, diff, gradW);
+                    sum += m_j / rho_j * dot(dim, diff, gradW);
                 }
             }
             drhodt[a_q] = 2.0 * rho_i * sum;
@@ -635,7 +673,7 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                  const double *wn, int64_t nq, const int64_t *qidx, double *acc)
 {
     int dim = P->dim;
-    double h = P->h, rc2 = 4.0 * h * h, m = particle_mass(P);
+    double h = P->h, rc2 = 4.0 * h * h;
     double eta2 = 0.01 * h * h;
     cellset sf, sw;
     int rc = cs_build(&sf, dim, nf, fx, 2.0 * h);
@@ -653,7 +691,8 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
         for (int64_t a_q = 0; a_q < nq; ++a_q) {
             int64_t i = qidx ? qidx[a_q] : a_q;
             const double *xi = fx + i * dim, *vi = fv + i * dim;
-            double rho_i = frho[i], p_i = eos_p(P, rho_i);
+            double rho_i = frho[i], p_i = eos_p(P, i, rho_i);
+            int penalised = P->penalty_on || is_light(P, i);
             double A[3] = {0, 0, 0};     /* pressure part, Eq. (10)/(11) */
             double Vis[3] = {0, 0, 0};   /* viscous part */
             double Fp[3] = {0, 0, 0};    /* penalty part, Eq. (13) */
@@ -680,24 +719,26 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                         e[k] = -rij[k] / r;
                         gradW[k] = dW * rij[k] / r;
                     }
-                    double rho_j, pstar;
+                    double rho_j, pstar, m;
                     if (set == 0) {
                         for (int k = 0; k < dim; ++k) vj[k] = fv[j * dim + k];
                         rho_j = frho[j];
-                        double p_j = eos_p(P, rho_j);
+                        double p_j = eos_p(P, j, rho_j);
                         riemann_out rs =
                             riemann(rho_i, dot(dim, vi, e), p_i, rho_j, dot(dim, vj, e), p_j, P->c);
                         pstar = rs.pstar;
+                        m = mass_of(P, j);
                     } else {
                         double p_w = pw[j];
-                        rho_j = eos_rho(P, p_w);
+                        rho_j = eos_rho(P, i, p_w);
                         pstar = (rho_i * p_w + rho_j * p_i) / (rho_i + rho_j); /* Eq. (11) */
+                        m = mass_of(P, i);
                     }
                     for (int k = 0; k < dim; ++k) A[k] += -2.0 * m * pstar / (rho_i * rho_j) * gradW[k];
                     /* viscous: 2 mu m_j/(rho_i rho_j) (r_ij . grad W)/(r^2 + eta^2) v_ij */
                     double visc = 2.0 * P->mu * m / (rho_i * rho_j) * dot(dim, rij, gradW) / (r2 + eta2);
                     for (int k = 0; k < dim; ++k) Vis[k] += visc * (vi[k] - vj[k]);
-                    if (set == 1 && P->penalty_on) {
+                    if (set == 1 && penalised) {
                         const double *n_w = wn + j * dim;
                         /* Eq. (15) with the magnitude of the normal projection */
                         double delta = 2.0 * fabs(dot(dim, rij, n_w)) / P->dx;
@@ -727,10 +768,10 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
 void orc_diag(const orc_params *P, int64_t nf, const double *fx, const double *fv, double *out)
 {
     int dim = P->dim;
-    double m = particle_mass(P);
     double M = 0, Pm[3] = {0, 0, 0}, Ek = 0, Ep = 0, vmax = 0;
     for (int64_t i = 0; i < nf; ++i) {
         const double *v = fv + i * dim, *x = fx + i * dim;
+        double m = mass_of(P, i);
         M += m;
         for (int k = 0; k < dim; ++k) Pm[k] += m * v[k];
         double v2 = dot(dim, v, v);
@@ -787,10 +828,16 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
             for (int a = 0; a < nprobe; ++a) s += pw[probe[a]];
             *J += dt * s / nprobe;
         }
-        /* Eqs. (9), (21): density update. */
+        /* Eqs. (9), (21): density update; in a two-phase run the light
+         * phase takes rho0_light sigma/sigma0 at r^{n+1} instead. */
         rc = orc_continuity(P, nf, fx, vhalf, rho_t, nw, wx, pw, nf, NULL, D);
         if (rc) break;
         for (int64_t i = 0; i < nf; ++i) frho[i] = rho_t[i] + dt * D[i];
+        if (P->two_phase && P->n_heavy < nf) {
+            rc = orc_sigma(P, nf, fx, nw, wx, nf, NULL, sigma);
+            if (rc) break;
+            for (int64_t i = P->n_heavy; i < nf; ++i) frho[i] = P->rho0_light * sigma[i] / P->sigma0;
+        }
         /* Eqs. (10), (22): acceleration at n+1 and second half kick. */
         rc = orc_momentum(P, nf, fx, vhalf, frho, nw, wx, pw, wn, nf, NULL, facc);
         if (rc) break;

@@ -49,6 +49,10 @@ class Scene:
     penalty_all: bool = True
     probe: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int64))
     meta: dict = field(default_factory=dict)
+    # two phases: fluid particles [0, n_heavy) are the heavy phase (rho0),
+    # the rest the light phase with reference density rho0_light
+    n_heavy: int | None = None
+    rho0_light: float | None = None
 
     @property
     def n_fluid(self) -> int:
@@ -100,6 +104,31 @@ def tank_walls(dim, n_in, n_top, dx, layers=3):
     inside &= ijk[:, dim - 1] >= 0
     ijk = ijk[~inside]
     return (ijk.astype(np.float64) + 0.5) * dx
+
+
+def closed_tank_walls(dim, n_in, n_top, dx, layers=3):
+    """Wall dummies of a closed tank (floor, sides and lid, ``layers`` rows
+    thick) around an interior of n_in[k] lattice columns per horizontal axis
+    and n_top rows in height."""
+    lo = [-layers] * dim
+    hi = [n + layers for n in n_in] + [n_top + layers]
+    idx = [np.arange(lo[k], hi[k]) for k in range(dim)]
+    grids = np.meshgrid(*idx[::-1], indexing="ij")
+    ijk = np.stack([g.ravel() for g in grids[::-1]], axis=1)
+    inside = np.ones(len(ijk), dtype=bool)
+    for k in range(dim - 1):
+        inside &= (ijk[:, k] >= 0) & (ijk[:, k] < n_in[k])
+    inside &= (ijk[:, dim - 1] >= 0) & (ijk[:, dim - 1] < n_top)
+    ijk = ijk[~inside]
+    return (ijk.astype(np.float64) + 0.5) * dx
+
+
+def _two_phase_rho(z, H, top, rho_w, rho_a, c0, heavy):
+    """Initial densities whose linear-EOS pressures are the two-layer
+    hydrostatic profile: rho_a g (top - z) in the air, rho_a g (top - H) +
+    rho_w g (H - z) in the water."""
+    p = np.where(heavy, rho_a * G * (top - H) + rho_w * G * (H - z), rho_a * G * (top - z))
+    return np.where(heavy, rho_w, rho_a) + p / (c0 * c0)
 
 
 def _hydrostatic_rho(z, H, rho0, c0):
@@ -267,6 +296,54 @@ def random_box(dim=3, n=1500, seed=0, dx=0.01, box_cells=None, walls=True, H=0.3
                  time_step(h, c0), 1, H, fx, fv, rho, wx, lo, hi)
 
 
+RHO_AIR = 1.0  # reference density of air (Sec. 4.1)
+
+
+def two_phase_tank_2d(dx=0.01, L=1.0, H=0.5, top=1.0, mu=0.0, steps=200, rho_air=RHO_AIR):
+    """2-D two-phase hydrostatic tank (Sec. 4.1): an L x top closed tank,
+    water below z = H, air above, both at rest on one square lattice; water
+    particles come first.  Inviscid as in the paper; the penalty acts on the
+    light phase only; one sound speed c0 = 10 sqrt(2 g H) for both phases."""
+    nx = int(round(L / dx))
+    nzw = int(round(H / dx))
+    nz = int(round(top / dx))
+    pts = _lattice([nx, nz], dx)
+    heavy = pts[:, 1] < H
+    fx = np.concatenate([pts[heavy], pts[~heavy]])
+    is_heavy = np.arange(len(fx)) < int(heavy.sum())
+    wx = closed_tank_walls(2, [nx], nz, dx)
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    rho = _two_phase_rho(fx[:, 1], H, top, RHO_WATER, rho_air, c0, is_heavy)
+    lo, hi = _box([-3.5 * dx, -3.5 * dx], [L + 3.5 * dx, top + 3.5 * dx])
+    return Scene("two_phase_tank_2d", 2, dx, h, RHO_WATER, c0, mu, 1.0, np.array([0.0, -G, 0.0]),
+                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi, penalty_all=False,
+                 meta=dict(L=L, top=top, nzw=nzw), n_heavy=int(heavy.sum()), rho0_light=rho_air)
+
+
+def dam_break_3d_two_phase(dx=0.005, mu=0.0, steps=1000, rho_air=RHO_AIR):
+    """3-D two-phase dam break: the water column of the 3-D dam break (0.6 x
+    0.6 x 0.3 m in a 1.6 x 0.6 x 0.6 m tank) with air on every other lattice
+    site of the tank, which is closed by a lid; water particles come first."""
+    tank = (1.6, 0.6, 0.6)
+    H = 0.3
+    n = [int(round(t / dx)) for t in tank]
+    pts = _lattice(n, dx)
+    heavy = (pts[:, 0] < 0.6) & (pts[:, 2] < H)
+    fx = np.concatenate([pts[heavy], pts[~heavy]])
+    is_heavy = np.arange(len(fx)) < int(heavy.sum())
+    wx = closed_tank_walls(3, n[:2], n[2], dx)
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    top = tank[2]
+    rho = np.where(is_heavy, _hydrostatic_rho(fx[:, 2], H, RHO_WATER, c0),
+                   rho_air + rho_air * G * (top - fx[:, 2]) / (c0 * c0))
+    lo, hi = _box([-3.5 * dx] * 3, [tank[0] + 3.5 * dx, tank[1] + 3.5 * dx, tank[2] + 3.5 * dx])
+    return Scene("dam_break_3d_two_phase", 3, dx, h, RHO_WATER, c0, mu, 1.0, np.array([0.0, 0.0, -G]),
+                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi, penalty_all=False,
+                 meta=dict(tank=tank), n_heavy=int(heavy.sum()), rho0_light=rho_air)
+
+
 def by_name(name: str, **kw) -> Scene:
     table = {
         "hydrostatic_tank_2d": hydrostatic_tank_2d,
@@ -275,5 +352,7 @@ def by_name(name: str, **kw) -> Scene:
         "dam_break_2d": dam_break_2d,
         "wall_jet_2d": wall_jet_2d,
         "random_box": random_box,
+        "two_phase_tank_2d": two_phase_tank_2d,
+        "dam_break_3d_two_phase": dam_break_3d_two_phase,
     }
     return table[name](**kw)
