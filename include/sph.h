@@ -80,8 +80,12 @@ typedef struct sph_desc {
     int32_t dim;         /* 2 or 3; the last axis is vertical */
     int32_t precision;   /* SPH_F32 or SPH_F64 */
     int32_t penalty_all; /* 1: the penalty force of Eq. (13) acts on every fluid-wall pair;
-                            0: no penalty (the paper applies it to the light phase only) */
-    int32_t reserved;
+                            0: on light-phase particles only (none in a single-phase run) */
+    int32_t two_phase;   /* 1: fluid particles whose initial index is >= n_heavy form the
+                            light phase (reference density rho0_light, same c0): reinitialised
+                            by Eq. (18), density from the number density after the drift
+                            instead of Eq. (9), Eq. (12) divided by rho_f term by term, wall
+                            dummies take the interacting particle's phase (Secs. 2.1-2.6) */
     double dx;           /* initial particle spacing (enters m = rho0 dx^d and Eq. (15)) */
     double h;            /* smoothing length; kernel support 2h (Sec. 4: h = 1.3 dx) */
     double rho0;         /* reference density, Eq. (3) */
@@ -93,6 +97,8 @@ typedef struct sph_desc {
     double a_wall[3];    /* wall acceleration in Eq. (12) */
     double lo[3];        /* lower corner of the cell grid */
     double hi[3];        /* upper corner of the cell grid */
+    int64_t n_heavy;     /* two-phase: number of heavy-phase particles (initial indices first) */
+    double rho0_light;   /* two-phase: reference density of the light phase */
     /* derived by sph_configure: */
     double cell;         /* cell edge L_c = 2h, rounded to T */
     double sigma0;       /* reference number density of Eq. (17): full lattice sum */
@@ -274,6 +280,8 @@ int sph_neighbours(const sph_desc *desc, const sph_buffers *buf, int which, cons
 /* frames (recomputed bit for bit, not differentiated); branches (the    */
 /* limiter, max() of Eq. (17), delta < 1) take the forward's side, with  */
 /* derivative 0 at max(x, 0)'s kink.  The adjoint runs in FP64.          */
+/* It covers the single-phase step: every backward call returns         */
+/* SPH_ERR_CONFIG when desc->two_phase is set.                          */
 /* ------------------------------------------------------------------ */
 
 #define SPH_THETA_MU 0

@@ -29,11 +29,11 @@ EXPORTED = ["sph_configure", "sph_scratch_bytes", "sph_init", "sph_build_cells",
 class Desc(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("precision", C.c_int32), ("penalty_all", C.c_int32),
-        ("reserved", C.c_int32),
+        ("two_phase", C.c_int32),
         ("dx", C.c_double), ("h", C.c_double), ("rho0", C.c_double), ("c0", C.c_double),
         ("mu", C.c_double), ("gamma_p", C.c_double), ("dt", C.c_double),
         ("g", C.c_double * 3), ("a_wall", C.c_double * 3), ("lo", C.c_double * 3),
-        ("hi", C.c_double * 3),
+        ("hi", C.c_double * 3), ("n_heavy", C.c_int64), ("rho0_light", C.c_double),
         ("cell", C.c_double), ("sigma0", C.c_double), ("grid", C.c_int32 * 3),
         ("reserved2", C.c_int32), ("n_cells", C.c_int64),
     ]

@@ -35,7 +35,17 @@ struct Par {
     T sigma0;        // reference number density of Eq. (17)
     T rho0_over_sigma0;
     T psi_min;       // normals with |Psi| <= psi_min are set to 0
+    int two_phase;   // 1: particles with initial index >= n_heavy are the light phase
+    int n_heavy;
+    T rho0L;         // light-phase reference density
+    T rho0L_over_sigma0;
 };
+
+// Reference density of the particle with initial index pid.
+template <typename T>
+__device__ __forceinline__ T ref_density(const Par<T>& P, int pid) {
+    return (P.two_phase && pid >= P.n_heavy) ? P.rho0L : P.rho0;
+}
 
 // Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8).
 // Renumber so that each XCD works on one contiguous range of particles: the

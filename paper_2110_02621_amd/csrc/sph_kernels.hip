@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_cellsort(const int32_t* __restrict__
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_gather_fluid(const int32_t* __restrict__ perm, int64_t n, const int32_t* __restrict__ key_in,
+    k_gather_fluid(Par<T> P, const int32_t* __restrict__ perm, int64_t n, const int32_t* __restrict__ key_in,
                    const int32_t* __restrict__ pid_in, const T* __restrict__ off_in,
                    const T* __restrict__ vel_in, const T* __restrict__ rho_in,
                    int32_t* __restrict__ key_out, int32_t* __restrict__ pid_out,
@@ -205,7 +205,8 @@ __global__ void __launch_bounds__(kBlock)
     if (i >= n) return;
     const int64_t s = perm[i];
     key_out[i] = key_in[s];
-    pid_out[i] = pid_in[s];
+    const int32_t id = pid_in[s];
+    pid_out[i] = id;
     const T r = rho_in[s];
     rho_out[i] = r;
     T o[3] = {0, 0, 0}, v[3] = {0, 0, 0};
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(kBlock)
         vel_out[k * n + i] = v[k];
     }
     pk_out[i] = Rec<T>{o[0], o[1], o[2], r};
-    vk_out[i] = Rec<T>{v[0], v[1], v[2], T(0)};
+    vk_out[i] = Rec<T>{v[0], v[1], v[2], ref_density(P, id)};
 }
 
 template <typename T, int D>
@@ -288,13 +289,13 @@ __global__ void __launch_bounds__(kBlock)
 // Initial velocity and density into the current copies (pid = input index).
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_init_state(int64_t n, const double* __restrict__ vel, const double* __restrict__ rho, T rho0,
+    k_init_state(Par<T> P, int64_t n, const double* __restrict__ vel, const double* __restrict__ rho,
                  int32_t* __restrict__ pid, T* __restrict__ vel_out, T* __restrict__ drho_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     pid[i] = (int32_t)i;
     for (int k = 0; k < D; ++k) vel_out[k * n + i] = T(vel[k * n + i]);
-    drho_out[i] = T(rho[i] - (double)rho0);
+    drho_out[i] = T(rho[i] - (double)ref_density(P, (int)i));
 }
 
 // ---------------------------------------------------------------------------
@@ -445,10 +446,18 @@ __global__ void __launch_bounds__(kBlock)
     }
     if (sigma_out) sigma_out[i] = s;
     // Eq. (17) in deviations from rho0: rho_s - rho0 = rho0 (sigma - sigma0)/sigma0.
-    const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
-    const T dstar = drho[i];
-    const T excess = dstar - drs;
-    const T dtil = excess > T(0) ? drs + excess * P.rho0 / (P.rho0 + dstar) : drs;
+    const int id = pid[i];
+    const bool light = P.two_phase && id >= P.n_heavy;
+    T dtil;
+    if (light) {
+        // Eq. (18), internal flow: rho - rho0_light = rho0_light (sigma - sigma0)/sigma0
+        dtil = P.rho0L_over_sigma0 * (s - P.sigma0);
+    } else {
+        const T drs = P.rho0_over_sigma0 * (s - P.sigma0);
+        const T dstar = drho[i];
+        const T excess = dstar - drs;
+        dtil = excess > T(0) ? drs + excess * P.rho0 / (P.rho0 + dstar) : drs;
+    }
     drho[i] = dtil;
     // Eqs. (19)-(20): half kick, drift, renormalise the cell.
     int cn[3] = {c[0], c[1], c[2]};
@@ -476,21 +485,21 @@ __global__ void __launch_bounds__(kBlock)
     }
     if (out) atomicAdd(&status[SPH_STATUS_OUT_OF_GRID], 1u);
     key_out[i] = cn[0] + P.nx * (cn[1] + P.ny * cn[2]);
-    pid_out[i] = pid[i];
+    pid_out[i] = id;
     // packed copies of the sorted state: same offsets, the new density and velocity
     pk[i] = Rec<T>{oi[0], oi[1], oi[2], dtil};
-    vk[i] = Rec<T>{vh[0], vh[1], vh[2], T(0)};
+    vk[i] = Rec<T>{vh[0], vh[1], vh[2], light ? P.rho0L : P.rho0};
 }
 
 // ---------------------------------------------------------------------------
 // Wall pressure, Eq. (12), one thread per wall particle.
 // ---------------------------------------------------------------------------
 
-template <typename T, int D>
+template <typename T, int D, bool MP>
 __global__ void __launch_bounds__(kBlock)
     k_wall_bc(Par<T> P, NbrMask LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
               const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
-              Rec<T>* __restrict__ wk, T* __restrict__ pw) {
+              const Rec<T>* __restrict__ vk, Rec<T>* __restrict__ wk, T* __restrict__ pw) {
     const int64_t w = global_index();
     if (w >= nw) return;
     int c[3];
@@ -500,14 +509,23 @@ __global__ void __launch_bounds__(kBlock)
     T sW = T(0), sP = T(0), sR[3] = {0, 0, 0};
     if (nf > 0)
         visit4<T, D>(P, LWF, w, fstart, PackSrc<T>{pk}, c, ow,
-                             [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+                             [&](int f, const T d[3], T r2, uint32_t, const Rec<T>& q) {
                                  const T W = wendland_W(P, root(r2));
                                  const T dr = q.w;
-                                 sW += W;
-                                 sP += P.c2 * dr * W;
-                                 const T rW = (P.rho0 + dr) * W;
+                                 if (MP) {
+                                     // two phases: Eq. (12) divided by rho_f term by term
+                                     const T rinv = T(1) / (ld4(vk, f).w + dr);
+                                     sW += W * rinv;
+                                     sP += P.c2 * dr * W * rinv;
 #pragma unroll
-                                 for (int k = 0; k < D; ++k) sR[k] += rW * d[k];
+                                     for (int k = 0; k < D; ++k) sR[k] += W * d[k];
+                                 } else {
+                                     sW += W;
+                                     sP += P.c2 * dr * W;
+                                     const T rW = (P.rho0 + dr) * W;
+#pragma unroll
+                                     for (int k = 0; k < D; ++k) sR[k] += rW * d[k];
+                                 }
                              });
     T gR = T(0);
 #pragma unroll
@@ -545,10 +563,10 @@ __global__ void __launch_bounds__(kBlock)
 // F [rho_j (v_ij . r_ij) + (p_i - p_j) r / c] / (rho_j (rho_i + rho_j)).
 // ---------------------------------------------------------------------------
 
-template <typename T, int D>
+template <typename T, int D, bool MP>
 __global__ void __launch_bounds__(kBlock)
     k_continuity(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
-                 const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
+                 const int32_t* __restrict__ pid, const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                  const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                  const Rec<T>* __restrict__ wk, T* __restrict__ drho_out, Rec<T>* __restrict__ pk_out) {
     __shared__ Rec<T> stage[2 * kWaves * kStage];
@@ -570,20 +588,26 @@ __global__ void __launch_bounds__(kBlock)
     const T oi[3] = {me.x, me.y, me.z};
     const T vi[3] = {mv.x, mv.y, mv.z};
     const T dri = me.w;
-    const T rho_i = P.rho0 + dri;
+    const bool light = MP && pid[i] >= P.n_heavy;
+    const T r0i = light ? P.rho0L : P.rho0;  // own reference density
+    const T rho_i = r0i + dri;
     T sum = T(0);
+    T sig = T(0), comp = T(0);  // two phases: sigma at these positions for the light phase
     auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
+        if (MP) kahan_add(sig, comp, wendland_W(P, root(r2)));
         if (!(r2 > T(0))) return;
         const T r = root(r2);
         const T F = wendland_F(P, r);
         const T drj = q.w;
-        const T rho_j = P.rho0 + drj;
+        const T r0j = MP ? vj.w : P.rho0;
+        const T rho_j = r0j + drj;
         const T vjk[3] = {vj.x, vj.y, vj.z};
         T vd = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) vd += (vi[k] - vjk[k]) * d[k];
         const T qq = rcp(rho_j * (rho_i + rho_j));
-        sum += F * qq * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
+        const T term = F * qq * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
+        sum += MP ? r0j * term : term;  // m_j = rho0_j dx^d
     };
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
@@ -593,18 +617,21 @@ __global__ void __launch_bounds__(kBlock)
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+                         if (MP) kahan_add(sig, comp, wendland_W(P, root(r2)));
                          if (!(r2 > T(0))) return;
                          const T r = root(r2);
                          const T F = wendland_F(P, r);
                          const T p_w = q.w;
-                         const T rho_w = P.rho0 + p_w * P.inv_c2;
+                         const T rho_w = r0i + p_w * P.inv_c2;  // the wall takes i's phase
                          T vd = T(0);
 #pragma unroll
                          for (int k = 0; k < D; ++k) vd += vi[k] * d[k];
                          const T qq = rcp(rho_w * (rho_i + rho_w));
-                         sum += F * qq * (rho_w * vd + (P.c2 * dri - p_w) * r * P.cinv);
+                         const T term = F * qq * (rho_w * vd + (P.c2 * dri - p_w) * r * P.cinv);
+                         sum += MP ? r0i * term : term;
                      });
-    const T dnew = dri + P.dt * (T(2) * rho_i * P.m * sum);
+    T dnew = MP ? dri + P.dt * (T(2) * rho_i * P.vol * sum) : dri + P.dt * (T(2) * rho_i * P.m * sum);
+    if (light) dnew = P.rho0L_over_sigma0 * (sig - P.sigma0);  // light phase: number density at r^{n+1}
     drho_out[i] = dnew;
     pk_out[i] = Rec<T>{me.x, me.y, me.z, dnew};
 }
@@ -617,10 +644,10 @@ __global__ void __launch_bounds__(kBlock)
 //   dv_i/dt += m F/(rho_i rho_j) [-2 p* r_ij + 2 mu r^2/(r^2 + eta^2) v_ij].
 // ---------------------------------------------------------------------------
 
-template <typename T, int D>
+template <typename T, int D, bool MP>
 __global__ void __launch_bounds__(kBlock)
     k_momentum(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
-               const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
+               const int32_t* __restrict__ pid, const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ nk, T* __restrict__ acc,
                T* __restrict__ vel_out, Rec<T>* __restrict__ vk_out, T* __restrict__ sigma_next,
@@ -644,7 +671,9 @@ __global__ void __launch_bounds__(kBlock)
     const T oi[3] = {me.x, me.y, me.z};
     const T vi[3] = {mv.x, mv.y, mv.z};
     const T dri = me.w;
-    const T rho_i = P.rho0 + dri;
+    const bool light = MP && pid[i] >= P.n_heavy;
+    const T r0i = light ? P.rho0L : P.rho0;  // own reference density
+    const T rho_i = r0i + dri;
     const T p_i = P.c2 * dri;
     const T inv_rho_i = T(1) / rho_i;
     T A[3] = {0, 0, 0};
@@ -658,7 +687,8 @@ __global__ void __launch_bounds__(kBlock)
         const T r = r2 * rinv;
         const T F = wendland_F(P, r);
         const T drj = q.w;
-        const T rho_j = P.rho0 + drj;
+        const T r0j = MP ? vj.w : P.rho0;
+        const T rho_j = r0j + drj;
         const T p_j = P.c2 * drj;
         const T vjk[3] = {vj.x, vj.y, vj.z};
         T dv[3];
@@ -673,7 +703,8 @@ __global__ void __launch_bounds__(kBlock)
         const T sum = rho_i + rho_j;
         const T qq = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
         const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * qq);
-        const T coef = P.m * F * (sum * qq) * inv_rho_i;  // m F/(rho_i rho_j)
+        const T mj = MP ? r0j * P.vol : P.m;
+        const T coef = mj * F * (sum * qq) * inv_rho_i;  // m_j F/(rho_i rho_j)
         const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
 #pragma unroll
         for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
@@ -691,15 +722,16 @@ __global__ void __launch_bounds__(kBlock)
                          const T r = root(r2);
                          const T F = wendland_F(P, r);
                          const T p_w = q.w;
-                         const T rho_w = P.rho0 + p_w * P.inv_c2;
+                         const T rho_w = r0i + p_w * P.inv_c2;  // the wall takes i's phase
                          const T sum = rho_i + rho_w;
                          const T qq = rcp(rho_w * sum);
                          const T pstar = (rho_i * p_w + rho_w * p_i) * (rho_w * qq);
-                         const T coef = P.m * F * (sum * qq) * inv_rho_i;
+                         const T mw = MP ? r0i * P.vol : P.m;
+                         const T coef = mw * F * (sum * qq) * inv_rho_i;
                          const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
                          T pen = T(0);
                          T nv[3] = {0, 0, 0};
-                         if (P.penalty) {
+                         if (P.penalty || light) {
                              const Rec<T> nw4 = ld4(nk, w);
                              nv[0] = nw4.x;
                              nv[1] = nw4.y;
@@ -726,7 +758,7 @@ __global__ void __launch_bounds__(kBlock)
         vn[k] = vi[k] + P.half_dt * a;
         if (kick) vel_out[k * nf + i] = vn[k];
     }
-    if (kick) vk_out[i] = Rec<T>{vn[0], vn[1], vn[2], T(0)};
+    if (kick) vk_out[i] = Rec<T>{vn[0], vn[1], vn[2], r0i};
     sigma_next[i] = s;
 }
 
@@ -794,7 +826,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // Exact FP64 particle mass and body force of the reductions (by value).
 struct DiagC {
-    double m;
+    double m, m_light;  // heavy (or only) and light phase particle masses
     double g[3];
 };
 
@@ -802,7 +834,7 @@ struct DiagC {
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_diag_partial(Par<T> P, GridD G, DiagC K, int64_t nf,
-                   const int32_t* __restrict__ key, const T* __restrict__ off,
+                   const int32_t* __restrict__ key, const int32_t* __restrict__ pid, const T* __restrict__ off,
                    const T* __restrict__ vel, const T* __restrict__ drho, double* __restrict__ part) {
     __shared__ double red[kDiagVals][kBlock];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -811,18 +843,19 @@ __global__ void __launch_bounds__(kBlock)
         int c[3];
         cell_of(P, key[i], c);
         double v2 = 0.0, gx = 0.0;
+        const double m = (P.two_phase && pid[i] >= P.n_heavy) ? K.m_light : K.m;
         bool finite = isfinite((double)drho[i]);
         for (int k = 0; k < D; ++k) {
             const double vk = (double)vel[k * nf + i];
             const double xk = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
             finite = finite && isfinite(vk) && isfinite(xk);
-            v[1 + k] = K.m * vk;
+            v[1 + k] = m * vk;
             v2 += vk * vk;
             gx += K.g[k] * xk;
         }
-        v[0] = K.m;
-        v[4] = 0.5 * K.m * v2;
-        v[5] = -K.m * gx;
+        v[0] = m;
+        v[4] = 0.5 * m * v2;
+        v[5] = -m * gx;
         v[6] = sqrt(v2);
         v[7] = finite ? 0.0 : 1.0;
     }
@@ -899,7 +932,7 @@ __global__ void __launch_bounds__(kBlock)
         if (vel_o) vel_o[k * nf + p] = (double)vel[k * nf + i];
         if (acc_o) acc_o[k * nf + p] = (double)acc[k * nf + i];
     }
-    if (rho_o) rho_o[p] = (double)P.rho0 + (double)drho[i];
+    if (rho_o) rho_o[p] = (double)ref_density(P, (int)p) + (double)drho[i];
 }
 
 template <typename T, int D>
@@ -995,7 +1028,7 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     if (rc) return rc;
     if (n > 0) {
         const int sv = b->sel_vel, sr = b->sel_rho;
-        hipLaunchKernelGGL((k_gather_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, s.perm, n,
+        hipLaunchKernelGGL((k_gather_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, make_par<T>(d), s.perm, n,
                            b->key[1], b->pid[1], (const T*)b->off[1], (const T*)b->vel[sv],
                            (const T*)b->rho[sr], b->key[0], b->pid[0], (T*)b->off[0],
                            (T*)b->vel[1 - sv], (T*)b->rho[1 - sr], (Rec<T>*)s.pk[1 - sr],
@@ -1049,8 +1082,14 @@ int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = tr
     if (nw == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
     const Scratch s = layout(d, nf, nw, b->scratch);
-    hipLaunchKernelGGL((k_wall_bc<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf, nw,
-                       b->wkey, b->fstart, (const Rec<T>*)s.pk[b->sel_rho], (Rec<T>*)s.wk, (T*)b->pw);
+    if (d->two_phase)
+        hipLaunchKernelGGL((k_wall_bc<T, D, true>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf,
+                           nw, b->wkey, b->fstart, (const Rec<T>*)s.pk[b->sel_rho],
+                           (const Rec<T>*)s.vk[b->sel_vel], (Rec<T>*)s.wk, (T*)b->pw);
+    else
+        hipLaunchKernelGGL((k_wall_bc<T, D, false>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf,
+                           nw, b->wkey, b->fstart, (const Rec<T>*)s.pk[b->sel_rho],
+                           (const Rec<T>*)s.vk[b->sel_vel], (Rec<T>*)s.wk, (T*)b->pw);
     SPH_LAUNCH_CHECK();
     if (probe && b->n_probe > 0) {
         hipLaunchKernelGGL((k_probe<T>), dim3(1), dim3(kBlock), 0, st, (const T*)b->pw, s.winv, nw,
@@ -1069,8 +1108,9 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     const Rec<T>* wk = (const Rec<T>*)s.wk;
     if (which & SPH_CONTINUITY) {
         if (nf > 0) {
-            hipLaunchKernelGGL((k_continuity<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->fstart,
+            auto kern = d->two_phase ? k_continuity<T, D, true> : k_continuity<T, D, false>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
+                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->pid[0], b->fstart,
                                (const Rec<T>*)s.pk[sr], (const Rec<T>*)s.vk[sv], b->wstart, wk,
                                (T*)b->rho[1 - sr], (Rec<T>*)s.pk[1 - sr]);
             SPH_LAUNCH_CHECK();
@@ -1079,8 +1119,9 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
     } else {
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
         if (nf > 0) {
-            hipLaunchKernelGGL((k_momentum<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
-                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->fstart,
+            auto kern = d->two_phase ? k_momentum<T, D, true> : k_momentum<T, D, false>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
+                               mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->pid[0], b->fstart,
                                (const Rec<T>*)s.pk[sr], (const Rec<T>*)s.vk[sv], b->wstart, wk,
                                (const Rec<T>*)s.nk, (T*)b->acc, (T*)b->vel[1 - sv],
                                (Rec<T>*)s.vk[1 - sv], (T*)s.sig, kick);
@@ -1132,8 +1173,8 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
         hipLaunchKernelGGL((k_to_cells<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, fpos, nf, G,
                            b->key[1], (T*)b->off[1], b->status);
         SPH_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_init_state<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, nf, fvel,
-                           frho, P.rho0, b->pid[1], (T*)b->vel[0], (T*)b->rho[0]);
+        hipLaunchKernelGGL((k_init_state<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, fvel,
+                           frho, b->pid[1], (T*)b->vel[0], (T*)b->rho[0]);
         SPH_LAUNCH_CHECK();
     }
     rc = build_cells_t<T, D>(d, b, st);
@@ -1210,10 +1251,12 @@ int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int nb = nf > 0 ? grid_for(nf) : 0;
     if (nb > 0) {
         DiagC K;
-        K.m = d->rho0 * (d->dim == 2 ? d->dx * d->dx : d->dx * d->dx * d->dx);
+        const double vol = d->dim == 2 ? d->dx * d->dx : d->dx * d->dx * d->dx;
+        K.m = d->rho0 * vol;
+        K.m_light = (d->two_phase ? d->rho0_light : d->rho0) * vol;
         for (int k = 0; k < 3; ++k) K.g[k] = d->g[k];
         hipLaunchKernelGGL((k_diag_partial<T, D>), dim3(nb), dim3(kBlock), 0, st, make_par<T>(d),
-                           make_grid(d), K, nf, b->key[0], (const T*)b->off[0],
+                           make_grid(d), K, nf, b->key[0], b->pid[0], (const T*)b->off[0],
                            (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], s.part);
         SPH_LAUNCH_CHECK();
     }
@@ -1274,6 +1317,9 @@ int sph_configure(sph_desc* d) {
     if (d->dim != 2 && d->dim != 3) return SPH_ERR_CONFIG;
     if (d->precision != SPH_F32 && d->precision != SPH_F64) return SPH_ERR_CONFIG;
     if (!(d->h > 0.0) || !(d->dx > 0.0) || !(d->c0 > 0.0) || !(d->rho0 > 0.0) || !(d->dt > 0.0))
+        return SPH_ERR_CONFIG;
+    if (d->two_phase != 0 && d->two_phase != 1) return SPH_ERR_CONFIG;
+    if (d->two_phase && (!(d->rho0_light > 0.0) || d->n_heavy < 0 || d->n_heavy > (int64_t)INT32_MAX))
         return SPH_ERR_CONFIG;
     // time step bound, Eqs. (23)-(24) with U_max = c0/10
     double gn = 0.0;

@@ -32,6 +32,10 @@ def make_desc(scene, precision="f32") -> abi.Desc:
     d.penalty_all = 1 if scene.penalty_all else 0
     d.dx, d.h, d.rho0, d.c0 = scene.dx, scene.h, scene.rho0, scene.c0
     d.mu, d.gamma_p, d.dt = scene.mu, scene.gamma_p, scene.dt
+    if getattr(scene, "rho0_light", None) is not None:
+        d.two_phase = 1
+        d.n_heavy = int(scene.n_heavy)
+        d.rho0_light = float(scene.rho0_light)
     for k in range(3):
         d.g[k] = float(scene.g[k])
         d.a_wall[k] = 0.0
