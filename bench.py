@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-4m", action="store_true", help="skip the dx = 0.003 m (4M fluid) point")
+    ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase dam break point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
@@ -200,6 +201,21 @@ def main():
         del S4
         torch.cuda.empty_cache()
 
+    # two-phase dam break: water column + air in the rest of the closed tank
+    tp = None
+    if not args.no_two_phase:
+        sct = scenes.dam_break_3d_two_phase(dx=0.005, steps=args.steps)
+        kt = max(10, args.steps // 2)
+        St, wallt, staget = timed_run(solver, sct, "f32", kt, max(2, args.warmup // 2))
+        nt = sct.n_fluid + sct.n_wall
+        tp = dict(workload=f"3-D two-phase dam break dx=0.005 m: {sct.n_heavy} water + "
+                           f"{sct.n_fluid - sct.n_heavy} air + {sct.n_wall} wall, rho 1000/1, one c0",
+                  value=nt * kt / wallt, ms_per_step=1e3 * wallt / kt, steps=kt,
+                  stage_ms={k: round(v, 4) for k, v in staget.items()}, status=St.status())
+        print(f"[bench] two-phase f32 {tp['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        del St
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         k64 = args.fp64_steps or args.steps
@@ -269,6 +285,7 @@ def main():
                    "parallelism": "single GPU"},
         "fluid_particle_steps_per_s": nf * args.steps / wall,
         "fp32_4M": m4,
+        "fp32_two_phase": tp,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
         "adjoint_fwd_ratio": adj["ratio"] if adj else None,
