@@ -130,3 +130,20 @@ def test_two_phase_hydrostatic_tank_fp32(solver_mod):
     print(f"  two-phase tank FP32: water pressure L2 error {err:.3e}", flush=True)
     assert err < 0.05
     assert S.status() == dict(out_of_grid=0, fast=0, nonfinite=0, list_overflow=0)
+
+
+def test_two_phase_tank_long_run_fp64_matches_oracle(solver_mod):
+    # 2 s of the Sec. 4.1 tank at dx = 0.04 (5300 steps): the FP64 HIP path
+    # follows the oracle's energy history step for step.
+    sc = scenes.two_phase_tank_2d(dx=0.04)
+    S = solver_mod.Solver(sc, "f64")
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+    n = int(round(2.0 / sc.dt))
+    for k in range(10):
+        S.step(n // 10)
+        st.step(n // 10)
+        d, od = S.diag(), st.diag()
+        e, oe = d["Ek"] + d["Ep"], od["Ek"] + od["Ep"]
+        assert abs(e - oe) < 1e-9 * abs(oe), (k, e, oe)
+        assert d["Ek"] == pytest.approx(od["Ek"], rel=1e-6, abs=1e-9)
