@@ -35,6 +35,9 @@ class OrcParams(C.Structure):
         ("reserved", C.c_int32),
         ("n_heavy", C.c_int64),
         ("rho0_light", C.c_double),
+        ("wall_v", C.c_double * 3),
+        ("motion_amp", C.c_double * 3),
+        ("motion_freq", C.c_double),
     ]
 
 
@@ -75,8 +78,10 @@ def lib():
         L.orc_momentum.argtypes = [pp, i64, dp, dp, dp, i64, dp, dp, dp, i64, qp, dp]
         L.orc_diag.argtypes = [pp, i64, dp, dp, dp]
         L.orc_diag.restype = None
-        L.orc_step.argtypes = [pp, i64, dp, dp, dp, dp, i64, dp, dp, dp, C.c_int, ip, C.c_int,
-                               dp, C.c_double]
+        L.orc_step.argtypes = [pp, i64, dp, dp, dp, dp, i64, dp, dp, dp, dp, i64, C.c_int, ip,
+                               C.c_int, dp, C.c_double]
+        L.orc_tank_motion.argtypes = [pp, i64, dp, dp, dp]
+        L.orc_tank_motion.restype = None
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -104,10 +109,14 @@ def _check(rc, what):
 
 def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
            a_wall=(0.0, 0.0, 0.0), sigma0=None, penalty_on=True, n_heavy=None,
-           rho0_light=None) -> OrcParams:
+           rho0_light=None, wall_v=(0.0, 0.0, 0.0), motion_amp=(0.0, 0.0, 0.0),
+           motion_freq=0.0) -> OrcParams:
     """Parameter block.  sigma0 defaults to the lattice sum of Eq. (17).
     Two phases: fluid particles with index >= n_heavy have reference density
-    rho0_light (both given, or neither for a single phase)."""
+    rho0_light (both given, or neither for a single phase).  wall_v is the
+    wall velocity seen by the pair functions; a time step takes it, and the
+    wall positions and acceleration, from the tank motion
+    X(t) = motion_amp sin(2 pi motion_freq t)."""
     p = OrcParams()
     p.dim = int(dim)
     p.penalty_on = 1 if penalty_on else 0
@@ -119,6 +128,10 @@ def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
     p.two_phase = 1 if rho0_light is not None else 0
     p.n_heavy = int(n_heavy) if n_heavy is not None else 0
     p.rho0_light = float(rho0_light) if rho0_light is not None else float(rho0)
+    for k in range(3):
+        p.wall_v[k] = float(wall_v[k]) if k < len(wall_v) else 0.0
+        p.motion_amp[k] = float(motion_amp[k]) if k < len(motion_amp) else 0.0
+    p.motion_freq = float(motion_freq)
     return p
 
 
@@ -127,6 +140,8 @@ def params_from_scene(sc, **over) -> OrcParams:
               gamma_p=sc.gamma_p, dt=sc.dt, g=tuple(sc.g), penalty_on=sc.penalty_all)
     if getattr(sc, "rho0_light", None) is not None:
         kw.update(n_heavy=sc.n_heavy, rho0_light=sc.rho0_light)
+    if getattr(sc, "motion_freq", 0.0):
+        kw.update(motion_amp=tuple(sc.motion_amp), motion_freq=sc.motion_freq)
     kw.update(over)
     return params(**kw)
 
@@ -288,8 +303,18 @@ def diag(P, fx, fv):
     return dict(M=out[0], P=out[1:4].copy(), Ek=out[4], Ep=out[5], vmax=out[6])
 
 
+def tank_motion(P, step):
+    """(X, V, A) of the prescribed tank motion at t = step dt, each (dim,)."""
+    X, V, A = np.zeros(3), np.zeros(3), np.zeros(3)
+    lib().orc_tank_motion(C.byref(P), int(step), _d(X), _d(V), _d(A))
+    return X[: P.dim], V[: P.dim], A[: P.dim]
+
+
 class State:
-    """Oracle state of one run: fluid arrays are updated in place by step()."""
+    """Oracle state of one run: fluid arrays are updated in place by step().
+
+    wx0 are the wall dummies at t = 0; with a tank motion they sit at
+    wx0 + X(t) (self.wx) and move with it."""
 
     def __init__(self, P, fx, fv, frho, wx, probe=None):
         d = P.dim
@@ -297,14 +322,18 @@ class State:
         self.x = _f64(fx, d).copy()
         self.v = _f64(fv, d).copy()
         self.rho = _f64(frho).copy()
-        self.wx = _f64(wx, d).copy()
+        self.wx0 = _f64(wx, d).copy()
+        self.nstep = 0
+        X, V, A = tank_motion(P, 0)
+        self.wx = self.wx0 + X
         self.wn = normals(P, self.wx)
-        # initial wall pressure and acceleration from the initial state
-        self.pw = wall_pressure(P, self.wx, self.x, self.rho)
-        self.a = momentum(P, self.x, self.v, self.rho, self.wx, self.pw, self.wn)
+        # initial wall pressure and acceleration from the initial state, the
+        # walls moving with X'(0) and accelerating with X''(0)
+        Q = params_copy(P, wall_v=V, a_wall=np.array(P.a_wall[:d]) + A)
+        self.pw = wall_pressure(Q, self.wx, self.x, self.rho)
+        self.a = momentum(Q, self.x, self.v, self.rho, self.wx, self.pw, self.wn)
         self.probe = None if probe is None else np.ascontiguousarray(probe, dtype=np.int32)
         self.J = 0.0
-        self.nstep = 0
 
     def step(self, n=1, damp=0.0):
         P = self.P
@@ -312,10 +341,13 @@ class State:
         pwb = np.zeros(max(len(self.wx), 1))
         pwb[: len(self.pw)] = self.pw
         nprobe = 0 if self.probe is None else len(self.probe)
+        wxb = self.wx.copy()
         _check(lib().orc_step(C.byref(P), len(self.x), _d(self.x), _d(self.v), _d(self.rho),
-                              _d(self.a), len(self.wx), _d(self.wx), _d(self.wn), _d(pwb), int(n),
+                              _d(self.a), len(self.wx0), _d(self.wx0), _d(wxb), _d(self.wn),
+                              _d(pwb), int(self.nstep), int(n),
                               _i(self.probe) if nprobe else None, nprobe, _d(Jb),
                               float(damp)), "step")
+        self.wx = wxb
         self.pw = pwb[: len(self.wx)].copy()
         self.J += float(Jb[0])
         self.nstep += n
@@ -323,6 +355,20 @@ class State:
 
     def diag(self):
         return diag(self.P, self.x, self.v)
+
+
+def params_copy(P, **over) -> OrcParams:
+    """A copy of a parameter block with some fields replaced (vectors padded)."""
+    q = OrcParams()
+    C.pointer(q)[0] = P
+    for k, v in over.items():
+        if isinstance(getattr(q, k), C.Array):
+            arr = getattr(q, k)
+            for i in range(3):
+                arr[i] = float(v[i]) if i < len(v) else 0.0
+        else:
+            setattr(q, k, v)
+    return q
 
 
 def num_threads() -> int:

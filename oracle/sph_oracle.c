@@ -29,7 +29,7 @@
  *   reinit      Eq. (17) at the start of every step with rho* = rho^n.
  *   viscosity   the paper is inviscid; the viscous term here is the
  *               Morris-Fox-Zhu (1997) form with eta^2 = 0.01 h^2, walls
- *               no-slip (v_w = 0).
+ *               no-slip (v_j = the wall velocity).
  *   penalty     Eqs. (13)-(15) with the unsigned normal distance
  *               delta = 2 |(r_i - r_w) . n_w| / dx (the magnitude of the
  *               projection, as in the penalty parameter itself) and the
@@ -55,6 +55,15 @@
  *               penalty_on).  The Riemann solution of Eqs. (7)-(8) is used
  *               as printed for pairs of either phase: its density weighting
  *               carries the density ratio.
+ *   moving walls a prescribed rigid translation of every wall dummy (the
+ *               tank), X(t) = A0 sin(2 pi f0 t) (Sec. 4, sloshing tank),
+ *               solved as it is stated, in the fixed frame: the walls sit at
+ *               x_w(0) + X(t_n); in the pair terms of a step (evaluated at
+ *               r^{n+1} with v^{n+1/2}) they move with the velocity of that
+ *               step's displacement, (X(t_{n+1}) - X(t_n))/dt, which enters
+ *               the Riemann states of Eq. (7), v* of Eq. (9) and the
+ *               no-slip viscous term; a_w of Eq. (12) is X''(t_{n+1}).  At
+ *               the initial state (t = 0) the walls move with X'(0).
  */
 #define _DEFAULT_SOURCE
 #include <math.h>
@@ -91,6 +100,10 @@ typedef struct {
     int32_t reserved;
     int64_t n_heavy;    /* number of heavy-phase fluid particles (indices first) */
     double rho0_light;  /* reference density of the light phase */
+    double wall_v[3];   /* velocity of the wall dummies in the pair terms (orc_step sets
+                           it from the tank motion) */
+    double motion_amp[3]; /* prescribed rigid translation of all walls (the tank):  */
+    double motion_freq;   /* X(t) = motion_amp sin(2 pi motion_freq t), t = step dt  */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -639,6 +652,7 @@ int orc_continuity(const orc_params *P, int64_t nf, const double *fx, const doub
                         p_j = eos_p(P, j, rho_j);
                         m_j = mass_of(P, j);
                     } else {
+                        for (int k = 0; k < dim; ++k) vj[k] = P->wall_v[k];
                         p_j = pw[j];
                         rho_j = eos_rho(P, i, p_j);
                         m_j = mass_of(P, i);
@@ -729,6 +743,7 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                         pstar = rs.pstar;
                         m = mass_of(P, j);
                     } else {
+                        for (int k = 0; k < dim; ++k) vj[k] = P->wall_v[k];
                         double p_w = pw[j];
                         rho_j = eos_rho(P, i, p_w);
                         pstar = (rho_i * p_w + rho_j * p_i) / (rho_i + rho_j); /* Eq. (11) */
@@ -787,18 +802,38 @@ void orc_diag(const orc_params *P, int64_t nf, const double *fx, const double *f
 }
 
 /* ------------------------------------------------------------------ */
+/* Prescribed tank motion: X(t) = A0 sin(2 pi f0 t) with its velocity  */
+/* and acceleration at t = step dt (all zero when f0 = 0).             */
+/* ------------------------------------------------------------------ */
+void orc_tank_motion(const orc_params *P, int64_t step, double *X, double *V, double *A)
+{
+    double w = 2.0 * M_PI * P->motion_freq, t = (double)step * P->dt;
+    for (int k = 0; k < 3; ++k) {
+        X[k] = P->motion_amp[k] * sin(w * t);
+        V[k] = P->motion_amp[k] * w * cos(w * t);
+        A[k] = -P->motion_amp[k] * w * w * sin(w * t);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Time stepping, Sec. 2.6: kick-drift-kick with the reinitialisation  */
 /* at the start of each step.  State arrays are updated in place.      */
 /*   fx, fv, frho, facc : fluid position, velocity, density, dv/dt     */
-/*   wx, wn             : fixed wall dummies and their normals         */
+/*   wx0                : wall dummies at t = 0                        */
+/*   wx                 : wall dummies at the end (x_w(0) + X(t))      */
+/*   wn                 : wall normals (a translation keeps them)      */
 /*   pw                 : wall pressure of the last step (output)      */
+/*   step0              : index n of the state passed in (t = n dt)    */
 /*   probe, nprobe, J   : optional; J += dt * mean_{w in probe} p_w    */
 /*   damp               : v *= (1 - damp) after every step (relaxation  */
 /*                        of a scene to rest; 0 for plain time steps)  */
+/* The wall velocity and acceleration of each step come from the tank  */
+/* motion (P->wall_v is not read).                                     */
 /* ------------------------------------------------------------------ */
 int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *frho,
-             double *facc, int64_t nw, const double *wx, const double *wn, double *pw,
-             int nsteps, const int32_t *probe, int nprobe, double *J, double damp)
+             double *facc, int64_t nw, const double *wx0, double *wx, const double *wn,
+             double *pw, int64_t step0, int nsteps, const int32_t *probe, int nprobe, double *J,
+             double damp)
 {
     int dim = P->dim;
     double dt = P->dt;
@@ -810,18 +845,30 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
     int rc = ORC_OK;
     if (!sigma || !rho_t || !vhalf || !D) rc = ORC_ERR_ALLOC;
     for (int n = 0; n < nsteps && rc == ORC_OK; ++n) {
+        double X0[3], V0[3], A0[3], X1[3], V1[3], A1[3];
+        orc_tank_motion(P, step0 + n, X0, V0, A0);
+        orc_tank_motion(P, step0 + n + 1, X1, V1, A1);
+        for (int64_t w = 0; w < nw; ++w)
+            for (int k = 0; k < dim; ++k) wx[w * dim + k] = wx0[w * dim + k] + X0[k];
         /* Eq. (17): reinitialise the density at r^n with rho* = rho^n. */
         rc = orc_sigma(P, nf, fx, nw, wx, nf, NULL, sigma);
         if (rc) break;
         orc_reinit(P, nf, sigma, frho, rho_t);
-        /* Eqs. (19)-(20): half kick and drift. */
+        /* Eqs. (19)-(20): half kick and drift; the walls move to X(t_{n+1}). */
         for (int64_t i = 0; i < nf; ++i)
             for (int k = 0; k < dim; ++k) {
                 vhalf[i * dim + k] = fv[i * dim + k] + 0.5 * dt * facc[i * dim + k];
                 fx[i * dim + k] = fx[i * dim + k] + dt * vhalf[i * dim + k];
             }
+        for (int64_t w = 0; w < nw; ++w)
+            for (int k = 0; k < dim; ++k) wx[w * dim + k] = wx0[w * dim + k] + X1[k];
+        orc_params Q = *P;
+        for (int k = 0; k < 3; ++k) {
+            Q.wall_v[k] = (X1[k] - X0[k]) / dt;
+            Q.a_wall[k] = P->a_wall[k] + A1[k];
+        }
         /* Eq. (12) at r^{n+1} from the reinitialised density. */
-        rc = orc_wall_pressure(P, nw, wx, nf, fx, rho_t, nw, NULL, pw);
+        rc = orc_wall_pressure(&Q, nw, wx, nf, fx, rho_t, nw, NULL, pw);
         if (rc) break;
         if (J && nprobe > 0) {
             double s = 0.0;
@@ -830,7 +877,7 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
         }
         /* Eqs. (9), (21): density update; in a two-phase run the light
          * phase takes rho0_light sigma/sigma0 at r^{n+1} instead. */
-        rc = orc_continuity(P, nf, fx, vhalf, rho_t, nw, wx, pw, nf, NULL, D);
+        rc = orc_continuity(&Q, nf, fx, vhalf, rho_t, nw, wx, pw, nf, NULL, D);
         if (rc) break;
         for (int64_t i = 0; i < nf; ++i) frho[i] = rho_t[i] + dt * D[i];
         if (P->two_phase && P->n_heavy < nf) {
@@ -839,7 +886,7 @@ int orc_step(const orc_params *P, int64_t nf, double *fx, double *fv, double *fr
             for (int64_t i = P->n_heavy; i < nf; ++i) frho[i] = P->rho0_light * sigma[i] / P->sigma0;
         }
         /* Eqs. (10), (22): acceleration at n+1 and second half kick. */
-        rc = orc_momentum(P, nf, fx, vhalf, frho, nw, wx, pw, wn, nf, NULL, facc);
+        rc = orc_momentum(&Q, nf, fx, vhalf, frho, nw, wx, pw, wn, nf, NULL, facc);
         if (rc) break;
         for (int64_t i = 0; i < nf; ++i)
             for (int k = 0; k < dim; ++k)
