@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-4m", action="store_true", help="skip the dx = 0.003 m (4M fluid) point")
     ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase dam break point")
+    ap.add_argument("--no-sloshing", action="store_true", help="skip the shaken two-phase tank points")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
@@ -216,6 +217,27 @@ def main():
         del St
         torch.cuda.empty_cache()
 
+    # the shaken two-phase tank of Sec. 4.4 (moving walls, X(t) = A0 sin(2 pi f0 t)):
+    # 243,432 particles at dx = 0.01 (the paper's kernel-profile case) and
+    # 1,410,752 at dx = 0.005 (its sloshing run)
+    slosh = None
+    if not args.no_sloshing:
+        slosh = []
+        for dxs in (0.01, 0.005):
+            scs = scenes.sloshing_tank(dim=3, dx=dxs, steps=args.steps)
+            ks = max(10, args.steps // 2)
+            Ss, walls_, stages = timed_run(solver, scs, "f32", ks, max(2, args.warmup // 2))
+            ns = scs.n_fluid + scs.n_wall
+            slosh.append(dict(workload=f"3-D two-phase sloshing tank 1.3 x 0.1 x 0.9 m, dx={dxs} m: "
+                                       f"{scs.n_heavy} water + {scs.n_fluid - scs.n_heavy} air + "
+                                       f"{scs.n_wall} wall, A0={scs.motion_amp[0]} m, f0={scs.motion_freq} Hz",
+                              value=ns * ks / walls_, ms_per_step=1e3 * walls_ / ks, steps=ks,
+                              stage_ms={k: round(v, 4) for k, v in stages.items()}, status=Ss.status()))
+            print(f"[bench] sloshing dx={dxs} f32 {slosh[-1]['ms_per_step']:.3f} ms/step",
+                  file=sys.stderr, flush=True)
+            del Ss
+            torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         k64 = args.fp64_steps or args.steps
@@ -286,6 +308,7 @@ def main():
         "fluid_particle_steps_per_s": nf * args.steps / wall,
         "fp32_4M": m4,
         "fp32_two_phase": tp,
+        "fp32_sloshing": slosh,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
         "adjoint_fwd_ratio": adj["ratio"] if adj else None,

@@ -32,6 +32,19 @@
  * Per-step schedule (sph_step runs exactly this):
  *   sph_density -> sph_build_cells -> sph_wall_bc -> sph_forces(CONTINUITY)
  *   -> sph_forces(MOMENTUM).
+ *
+ * Moving tank (desc->motion_freq != 0): every wall dummy translates rigidly
+ * with X(t).  The state is held in the tank's frame, where the walls stay
+ * where sph_init binned them: positions r - X(t), velocities v - u, where u
+ * is the tank velocity of the step's time level.  The step of the fixed
+ * frame maps onto it exactly: step n's drift moves the tank by
+ * X(t_{n+1}) - X(t_n) = dt Vh, so the half kick (sph_density) adds the
+ * uniform X'(t_n) - Vh, the walls are at rest relative to the fluid during
+ * the pair sweeps (in the fixed frame they move with Vh), Eq. (12) takes
+ * g - a_w - X''(t_{n+1}), and the second kick (sph_forces MOMENTUM) adds
+ * Vh - X'(t_{n+1}).  The stored dv/dt (acc) is the fixed-frame one.  Input
+ * (sph_init) and output (sph_export, sph_export_walls, sph_diag) are in the
+ * fixed frame at t = nstep dt; buf->nstep counts the steps.
  */
 #ifndef SPH_H
 #define SPH_H
@@ -46,7 +59,7 @@ extern "C" {
 #define SPH_OK 0
 #define SPH_ERR_ARG 1    /* null pointer, negative size, size mismatch, bad flag */
 #define SPH_ERR_CONFIG 2 /* dim not 2 or 3, precision unknown, dt above the CFL bound of
-                            Eqs. (23)-(24), grid too large, L_c < 2h */
+                            Eqs. (23)-(24), grid too large, L_c < 2h, bad motion */
 #define SPH_ERR_LAUNCH 3 /* a kernel launch failed (hipGetLastError after the launch) */
 
 #define SPH_F32 0
@@ -99,6 +112,9 @@ typedef struct sph_desc {
     double hi[3];        /* upper corner of the cell grid */
     int64_t n_heavy;     /* two-phase: number of heavy-phase particles (initial indices first) */
     double rho0_light;   /* two-phase: reference density of the light phase */
+    double motion_amp[3]; /* prescribed rigid translation of every wall dummy (the tank),   */
+    double motion_freq;   /* X(t) = motion_amp sin(2 pi motion_freq t) at t = nstep dt      */
+                          /* (Sec. 4.4); 0 = fixed walls.  See "Moving tank" below.        */
     /* derived by sph_configure: */
     double cell;         /* cell edge L_c = 2h, rounded to T */
     double sigma0;       /* reference number density of Eq. (17): full lattice sum */
@@ -160,6 +176,10 @@ typedef struct sph_buffers {
     uint64_t *nbr_fw;  /* fluid -> wall, uint64[rows][2][n_fluid] */
     uint64_t *nbr_wf;  /* wall -> fluid, uint64[rows][2][n_wall] */
     int32_t *cnt_ff, *cnt_fw, *cnt_wf;
+    /* Steps taken since sph_init (host side): set to 0 by sph_init and
+     * advanced by sph_density, whose drift starts a step; the time of the
+     * state is nstep * dt. */
+    int64_t nstep;
 } sph_buffers;
 
 /* Validates the run description and fills its derived fields: L_c = 2h
@@ -167,9 +187,10 @@ typedef struct sph_buffers {
  * density sum_j W of a full square/cubic lattice of spacing dx (the initial
  * reference value of Eq. (17)).  Host only.  SPH_ERR_CONFIG for dim not in
  * {2, 3}, unknown precision, h <= 0, dx <= 0, c0 <= 0, hi <= lo, more than
- * 2^31 - 2 cells, or dt more than 1 % above min(0.25 h/(1.1 c0),
- * 0.25 sqrt(h/|g|)) (Eqs. (23)-(24) with the anticipated maximum velocity
- * c0/10; the slack lets c0 be varied at a fixed dt). */
+ * 2^31 - 2 cells, a negative or non-finite motion_freq or non-finite
+ * motion_amp, or dt more than 1 % above min(0.25 h/(1.1 c0),
+ * 0.25 sqrt(h/a)) (Eqs. (23)-(24) with the anticipated maximum velocity
+ * c0/10; a = |g| + max |X''|; the slack lets c0 be varied at a fixed dt). */
 int sph_configure(sph_desc *desc);
 
 /* Bytes of scratch the calls need for n_fluid fluid and n_wall wall
@@ -188,6 +209,8 @@ size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
  *   fpos, fvel  device double[dim][n_fluid]  absolute positions, velocities
  *   frho        device double[n_fluid]       densities
  *   wpos        device double[dim][n_wall]   wall dummy positions
+ * Positions and velocities are those of t = 0 in the fixed frame (a moving
+ * tank subtracts X(0) and X'(0)); sets nstep = 0.
  * Converts positions to cell + offset, sorts walls by cell (once: they are
  * fixed, Sec. 2.3) and estimates their normals by Eq. (16), sorts the fluid
  * (sph_build_cells), computes the initial wall pressure (Eq. (12)) and
@@ -212,13 +235,14 @@ int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
  * Writes the new density and the half-step velocity in place (current
  * copies) and the drifted positions to key[1], off[1], pid[1].  When
  * sigma_ready is set, sigma comes from the momentum sweep at these
- * positions (the same pairs summed in the same order, so the same bits). */
+ * positions (the same pairs summed in the same order, so the same bits).
+ * A moving tank adds X'(t_n) - Vh to the kick; nstep advances by one. */
 int sph_density(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Wall dummy pressure by force balance with the fluid, Eq. (12), for every
  * wall particle from the current fluid positions and densities:
  * p_w = [sum_f p_f W_wf + (g - a_w) . sum_f rho_f r_wf W_wf] / sum_f W_wf,
- * 0 when no fluid particle is within 2h.  If a probe is set, adds
+ * 0 when no fluid particle is within 2h; a_w = a_wall + X''(nstep dt).  If a probe is set, adds
  * dt * mean(p_w over the probe) to diag[SPH_DIAG_PROBE]. */
 int sph_wall_bc(const sph_desc *desc, sph_buffers *buf, void *stream);
 
@@ -230,7 +254,8 @@ int sph_wall_bc(const sph_desc *desc, sph_buffers *buf, void *stream);
  * SPH_MOMENTUM: dv_i/dt of Eq. (10) with p* of Eq. (8) (fluid) and
  *   Eq. (11) (walls), the viscous term, the penalty force of Eqs. (13)-(15)
  *   if penalty_all, and g; stores it in acc and, unless SPH_NO_KICK, the
- *   velocity of Eq. (22) into the other velocity copy; swaps sel_vel.
+ *   velocity of Eq. (22) into the other velocity copy (a moving tank adds
+ *   Vh - X'(t_{n+1}), n + 1 = nstep); swaps sel_vel.
  *   The same sweep sums sigma_i of Eq. (4) for the next density update
  *   into the scratch and sets sigma_ready.
  * Exactly one of the two may be given per call. */
@@ -240,20 +265,21 @@ int sph_forces(const sph_desc *desc, sph_buffers *buf, unsigned which, void *str
 int sph_step(const sph_desc *desc, sph_buffers *buf, int nsteps, void *stream);
 
 /* FP64 global reductions into diag (mass, momentum, energies, max |v|;
- * deterministic order).  Non-finite values are counted in
+ * deterministic order; fixed-frame positions and velocities at nstep dt).  Non-finite values are counted in
  * SPH_STATUS_NONFINITE.  The probe entry and the step count are kept. */
 int sph_diag(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Copies the fluid state out in particle-id order as doubles (device
  * arrays, any may be NULL): pos double[dim][n_fluid] absolute positions,
  * vel double[dim][n_fluid], rho double[n_fluid] (full density),
- * acc double[dim][n_fluid]. */
+ * acc double[dim][n_fluid]; positions and velocities in the fixed frame at
+ * t = nstep dt (between steps). */
 int sph_export(const sph_desc *desc, const sph_buffers *buf, double *pos, double *vel,
                double *rho, double *acc, void *stream);
 
 /* Copies wall pressure (double[n_wall]), normals (double[dim][n_wall]) and
- * absolute positions as held (double[dim][n_wall]) out in wall-id order
- * (device arrays, any may be NULL). */
+ * absolute positions (double[dim][n_wall], fixed frame at t = nstep dt) out
+ * in wall-id order (device arrays, any may be NULL). */
 int sph_export_walls(const sph_desc *desc, const sph_buffers *buf, double *pw, double *nrm,
                      double *pos, void *stream);
 
@@ -280,8 +306,9 @@ int sph_neighbours(const sph_desc *desc, const sph_buffers *buf, int which, cons
 /* frames (recomputed bit for bit, not differentiated); branches (the    */
 /* limiter, max() of Eq. (17), delta < 1) take the forward's side, with  */
 /* derivative 0 at max(x, 0)'s kink.  The adjoint runs in FP64.          */
-/* It covers the single-phase step: every backward call returns         */
-/* SPH_ERR_CONFIG when desc->two_phase is set.                          */
+/* It covers the single-phase step in a fixed tank: every backward call */
+/* returns SPH_ERR_CONFIG when desc->two_phase or desc->motion_freq is   */
+/* set.                                                                  */
 /* ------------------------------------------------------------------ */
 
 #define SPH_THETA_MU 0

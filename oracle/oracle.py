@@ -335,6 +335,26 @@ class State:
         self.probe = None if probe is None else np.ascontiguousarray(probe, dtype=np.int32)
         self.J = 0.0
 
+    @classmethod
+    def resume(cls, P, x, v, rho, a, wx0, nstep, pw=None, probe=None):
+        """A state taken over mid-run: fluid arrays at step nstep (a = the
+        dv/dt of the last momentum evaluation), walls at wx0 + X(t)."""
+        d = P.dim
+        st = cls.__new__(cls)
+        st.P = P
+        st.x = _f64(x, d).copy()
+        st.v = _f64(v, d).copy()
+        st.rho = _f64(rho).copy()
+        st.a = _f64(a, d).copy()
+        st.wx0 = _f64(wx0, d).copy()
+        st.nstep = int(nstep)
+        st.wx = st.wx0 + tank_motion(P, st.nstep)[0]
+        st.wn = normals(P, st.wx)
+        st.pw = np.zeros(len(st.wx)) if pw is None else _f64(pw).copy()
+        st.probe = None if probe is None else np.ascontiguousarray(probe, dtype=np.int32)
+        st.J = 0.0
+        return st
+
     def step(self, n=1, damp=0.0):
         P = self.P
         Jb = np.zeros(1)

@@ -34,6 +34,7 @@ class Desc(C.Structure):
         ("mu", C.c_double), ("gamma_p", C.c_double), ("dt", C.c_double),
         ("g", C.c_double * 3), ("a_wall", C.c_double * 3), ("lo", C.c_double * 3),
         ("hi", C.c_double * 3), ("n_heavy", C.c_int64), ("rho0_light", C.c_double),
+        ("motion_amp", C.c_double * 3), ("motion_freq", C.c_double),
         ("cell", C.c_double), ("sigma0", C.c_double), ("grid", C.c_int32 * 3),
         ("reserved2", C.c_int32), ("n_cells", C.c_int64),
     ]
@@ -52,6 +53,7 @@ class Buffers(C.Structure):
         ("probe", C.c_void_p), ("n_probe", C.c_int32), ("sigma_ready", C.c_int32),
         ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
         ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p),
+        ("nstep", C.c_int64),
     ]
 
 

@@ -70,6 +70,7 @@ def save_state(S):
     st = {k: c[k].clone() for k in ("key", "pid", "off", "fstart", "vel", "rho", "acc", "pw")}
     for k in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
         st[k] = S.t[k].clone()
+    st["nstep"] = int(S.buf.nstep)
     return st
 
 
@@ -80,6 +81,7 @@ def load_state(S, st):
     for k in ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf"):
         S.t[k].copy_(st[k])
     S.buf.sigma_ready = 0  # the stored sigma belongs to the overwritten state
+    S.buf.nstep = st["nstep"]
 
 
 MASKS = ("nbr_ff", "nbr_fw", "nbr_wf", "cnt_ff", "cnt_fw", "cnt_wf")

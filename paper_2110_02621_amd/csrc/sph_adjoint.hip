@@ -618,7 +618,8 @@ AdjWork adj_layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
 }
 
 int check_adj(const sph_desc* d, const sph_buffers* b, const sph_adjoint* a) {
-    if (d->two_phase) return SPH_ERR_CONFIG;  // the backward covers the single-phase step
+    if (d->two_phase || d->motion_freq != 0.0)
+        return SPH_ERR_CONFIG;  // the backward covers the single-phase step in a fixed tank
     if (!a || !a->theta || !a->work) return SPH_ERR_ARG;
     if (a->work_bytes < sph_adjoint_work_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
     if (((uintptr_t)a->work & 255) != 0) return SPH_ERR_ARG;

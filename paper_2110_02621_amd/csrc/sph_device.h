@@ -39,6 +39,7 @@ struct Par {
     int n_heavy;
     T rho0L;         // light-phase reference density
     T rho0L_over_sigma0;
+    T fk[3];         // uniform velocity added by this call's kick (moving tank; else 0)
 };
 
 // Reference density of the particle with initial index pid.

@@ -24,7 +24,35 @@ struct GridD {
     double lo[3];
     double L;
     int n[3];
+    double X[3], V[3];  // tank position and velocity in the fixed frame (moving tank; else 0)
 };
+
+// Prescribed tank motion X(t) = A0 sin(2 pi f t) at t = step dt, with its
+// velocity and acceleration (all 0 for a fixed tank).
+struct Motion {
+    double X[3], V[3], A[3];
+};
+
+inline bool moving(const sph_desc* d) { return d->motion_freq != 0.0; }
+
+inline Motion motion_at(const sph_desc* d, int64_t step) {
+    Motion m;
+    const double w = 2.0 * M_PI * d->motion_freq, t = (double)step * d->dt;
+    const double s = std::sin(w * t), c = std::cos(w * t);
+    for (int k = 0; k < 3; ++k) {
+        const double a = moving(d) && k < d->dim ? d->motion_amp[k] : 0.0;
+        m.X[k] = a * s;
+        m.V[k] = a * w * c;
+        m.A[k] = -a * w * w * s;
+    }
+    return m;
+}
+
+// Tank velocity over the drift of step n: (X(t_{n+1}) - X(t_n)) / dt.
+inline void drift_velocity(const sph_desc* d, int64_t n, double Vh[3]) {
+    const Motion a = motion_at(d, n), b = motion_at(d, n + 1);
+    for (int k = 0; k < 3; ++k) Vh[k] = (b.X[k] - a.X[k]) / d->dt;
+}
 
 template <typename T>
 inline Par<T> make_par(const sph_desc* d) {
@@ -76,6 +104,18 @@ inline GridD make_grid(const sph_desc* d) {
         G.n[k] = d->grid[k];
     }
     G.L = d->cell;
+    for (int k = 0; k < 3; ++k) G.X[k] = G.V[k] = 0.0;
+    return G;
+}
+
+// Grid with the tank's position and velocity at t = step dt.
+inline GridD make_grid_at(const sph_desc* d, int64_t step) {
+    GridD G = make_grid(d);
+    const Motion m = motion_at(d, step);
+    for (int k = 0; k < 3; ++k) {
+        G.X[k] = m.X[k];
+        G.V[k] = m.V[k];
+    }
     return G;
 }
 

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(kBlock)
     bool outside = false;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double x = pos[k * n + i] - G.lo[k];
+        const double x = (pos[k * n + i] - G.X[k]) - G.lo[k];
         double f = floor(x / G.L);
         int ck = (int)fmax(fmin(f, (double)(G.n[k] - 1)), 0.0);
         if (!(f >= 0.0 && f <= (double)(G.n[k] - 1))) outside = true;
@@ -289,12 +289,13 @@ __global__ void __launch_bounds__(kBlock)
 // Initial velocity and density into the current copies (pid = input index).
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-    k_init_state(Par<T> P, int64_t n, const double* __restrict__ vel, const double* __restrict__ rho,
-                 int32_t* __restrict__ pid, T* __restrict__ vel_out, T* __restrict__ drho_out) {
+    k_init_state(Par<T> P, GridD G, int64_t n, const double* __restrict__ vel,
+                 const double* __restrict__ rho, int32_t* __restrict__ pid, T* __restrict__ vel_out,
+                 T* __restrict__ drho_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     pid[i] = (int32_t)i;
-    for (int k = 0; k < D; ++k) vel_out[k * n + i] = T(vel[k * n + i]);
+    for (int k = 0; k < D; ++k) vel_out[k * n + i] = T(vel[k * n + i] - G.V[k]);
     drho_out[i] = T(rho[i] - (double)ref_density(P, (int)i));
 }
 
@@ -466,7 +467,7 @@ __global__ void __launch_bounds__(kBlock)
     T vh[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const T v = vel[k * nf + i] + P.half_dt * acc[k * nf + i];
+        const T v = vel[k * nf + i] + P.half_dt * acc[k * nf + i] + P.fk[k];
         vel[k * nf + i] = v;
         vh[k] = v;
         T o = oi[k] + P.dt * v;
@@ -755,7 +756,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int k = 0; k < D; ++k) {
         const T a = A[k] + P.g[k];
         acc[k * nf + i] = a;
-        vn[k] = vi[k] + P.half_dt * a;
+        vn[k] = vi[k] + P.half_dt * a + P.fk[k];
         if (kick) vel_out[k * nf + i] = vn[k];
     }
     if (kick) vk_out[i] = Rec<T>{vn[0], vn[1], vn[2], r0i};
@@ -846,8 +847,8 @@ __global__ void __launch_bounds__(kBlock)
         const double m = (P.two_phase && pid[i] >= P.n_heavy) ? K.m_light : K.m;
         bool finite = isfinite((double)drho[i]);
         for (int k = 0; k < D; ++k) {
-            const double vk = (double)vel[k * nf + i];
-            const double xk = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
+            const double vk = (double)vel[k * nf + i] + G.V[k];
+            const double xk = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i] + G.X[k];
             finite = finite && isfinite(vk) && isfinite(xk);
             v[1 + k] = m * vk;
             v2 += vk * vk;
@@ -928,8 +929,8 @@ __global__ void __launch_bounds__(kBlock)
     int c[3];
     cell_of(P, key[i], c);
     for (int k = 0; k < D; ++k) {
-        if (pos_o) pos_o[k * nf + p] = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i];
-        if (vel_o) vel_o[k * nf + p] = (double)vel[k * nf + i];
+        if (pos_o) pos_o[k * nf + p] = G.lo[k] + (double)c[k] * G.L + (double)off[k * nf + i] + G.X[k];
+        if (vel_o) vel_o[k * nf + p] = (double)vel[k * nf + i] + G.V[k];
         if (acc_o) acc_o[k * nf + p] = (double)acc[k * nf + i];
     }
     if (rho_o) rho_o[p] = (double)ref_density(P, (int)p) + (double)drho[i];
@@ -949,7 +950,7 @@ __global__ void __launch_bounds__(kBlock)
     if (pw_o) pw_o[p] = (double)pw[w];
     for (int k = 0; k < D; ++k) {
         if (nrm_o) nrm_o[k * nw + p] = (double)nrm[k * nw + w];
-        if (pos_o) pos_o[k * nw + p] = G.lo[k] + (double)c[k] * G.L + (double)woff[k * nw + w];
+        if (pos_o) pos_o[k * nw + p] = G.lo[k] + (double)c[k] * G.L + (double)woff[k * nw + w] + G.X[k];
     }
 }
 
@@ -1062,8 +1063,15 @@ int density_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     const bool ready = b->sigma_ready != 0;
     b->sigma_ready = 0;  // the drift moves the positions it was summed at
+    const int64_t n = b->nstep++;
     if (nf == 0) return SPH_OK;
-    const Par<T> P = make_par<T>(d);
+    Par<T> P = make_par<T>(d);
+    if (moving(d)) {  // half kick in the tank frame: + X'(t_n) - Vh
+        double Vh[3];
+        drift_velocity(d, n, Vh);
+        const Motion m = motion_at(d, n);
+        for (int k = 0; k < 3; ++k) P.fk[k] = T(m.V[k] - Vh[k]);
+    }
     const Scratch s = layout(d, nf, nw, b->scratch);
     hipLaunchKernelGGL((k_density<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, mask_ff(b),
                        mask_fw(b), nf, nw,
@@ -1080,7 +1088,11 @@ template <typename T, int D>
 int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = true) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nw == 0) return SPH_OK;
-    const Par<T> P = make_par<T>(d);
+    Par<T> P = make_par<T>(d);
+    if (moving(d)) {  // Eq. (12) with a_w = a_wall + X''(t)
+        const Motion m = motion_at(d, b->nstep);
+        for (int k = 0; k < 3; ++k) P.gw[k] = T(d->g[k] - d->a_wall[k] - m.A[k]);
+    }
     const Scratch s = layout(d, nf, nw, b->scratch);
     if (d->two_phase)
         hipLaunchKernelGGL((k_wall_bc<T, D, true>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, mask_wf(b), nf,
@@ -1102,7 +1114,13 @@ int wall_bc_t(const sph_desc* d, sph_buffers* b, hipStream_t st, bool probe = tr
 template <typename T, int D>
 int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
-    const Par<T> P = make_par<T>(d);
+    Par<T> P = make_par<T>(d);
+    if (moving(d) && !(which & SPH_NO_KICK)) {  // second kick in the tank frame: + Vh - X'(t_{n+1})
+        double Vh[3];
+        drift_velocity(d, b->nstep - 1, Vh);
+        const Motion m = motion_at(d, b->nstep);
+        for (int k = 0; k < 3; ++k) P.fk[k] = T(Vh[k] - m.V[k]);
+    }
     const int sv = b->sel_vel, sr = b->sel_rho;
     const Scratch s = layout(d, nf, nw, b->scratch);
     const Rec<T>* wk = (const Rec<T>*)s.wk;
@@ -1138,7 +1156,8 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
            const double* frho, const double* wpos, hipStream_t st) {
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     const Scratch s = layout(d, nf, nw, b->scratch);
-    const GridD G = make_grid(d);
+    b->nstep = 0;
+    const GridD G = make_grid_at(d, 0);  // inputs are fixed-frame positions at t = 0
     const Par<T> P = make_par<T>(d);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, (int32_t*)b->status,
                        (int64_t)SPH_STATUS_LEN, 0);
@@ -1173,8 +1192,8 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
         hipLaunchKernelGGL((k_to_cells<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, fpos, nf, G,
                            b->key[1], (T*)b->off[1], b->status);
         SPH_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_init_state<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, nf, fvel,
-                           frho, b->pid[1], (T*)b->vel[0], (T*)b->rho[0]);
+        hipLaunchKernelGGL((k_init_state<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, P, G, nf,
+                           fvel, frho, b->pid[1], (T*)b->vel[0], (T*)b->rho[0]);
         SPH_LAUNCH_CHECK();
     }
     rc = build_cells_t<T, D>(d, b, st);
@@ -1256,7 +1275,7 @@ int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
         K.m_light = (d->two_phase ? d->rho0_light : d->rho0) * vol;
         for (int k = 0; k < 3; ++k) K.g[k] = d->g[k];
         hipLaunchKernelGGL((k_diag_partial<T, D>), dim3(nb), dim3(kBlock), 0, st, make_par<T>(d),
-                           make_grid(d), K, nf, b->key[0], b->pid[0], (const T*)b->off[0],
+                           make_grid_at(d, b->nstep), K, nf, b->key[0], b->pid[0], (const T*)b->off[0],
                            (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], s.part);
         SPH_LAUNCH_CHECK();
     }
@@ -1271,7 +1290,7 @@ int export_t(const sph_desc* d, const sph_buffers* b, double* pos, double* vel, 
     const int64_t nf = b->n_fluid;
     if (nf == 0) return SPH_OK;
     hipLaunchKernelGGL((k_export<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, make_par<T>(d),
-                       make_grid(d), nf, b->key[0], b->pid[0], (const T*)b->off[0],
+                       make_grid_at(d, b->nstep), nf, b->key[0], b->pid[0], (const T*)b->off[0],
                        (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho],
                        (const T*)b->acc, pos, vel, rho, acc);
     SPH_LAUNCH_CHECK();
@@ -1284,8 +1303,8 @@ int export_walls_t(const sph_desc* d, const sph_buffers* b, double* pw, double* 
     const int64_t nw = b->n_wall;
     if (nw == 0) return SPH_OK;
     hipLaunchKernelGGL((k_export_walls<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st,
-                       make_par<T>(d), make_grid(d), nw, b->wkey, b->wpid, (const T*)b->woff,
-                       (const T*)b->pw, (const T*)b->nrm, pw, nrm, pos);
+                       make_par<T>(d), make_grid_at(d, b->nstep), nw, b->wkey, b->wpid,
+                       (const T*)b->woff, (const T*)b->pw, (const T*)b->nrm, pw, nrm, pos);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
 }
@@ -1321,10 +1340,18 @@ int sph_configure(sph_desc* d) {
     if (d->two_phase != 0 && d->two_phase != 1) return SPH_ERR_CONFIG;
     if (d->two_phase && (!(d->rho0_light > 0.0) || d->n_heavy < 0 || d->n_heavy > (int64_t)INT32_MAX))
         return SPH_ERR_CONFIG;
-    // time step bound, Eqs. (23)-(24) with U_max = c0/10
+    if (!std::isfinite(d->motion_freq) || d->motion_freq < 0.0) return SPH_ERR_CONFIG;
+    double amp = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(d->motion_amp[k])) return SPH_ERR_CONFIG;
+        amp += d->motion_amp[k] * d->motion_amp[k];
+    }
+    // time step bound, Eqs. (23)-(24) with U_max = c0/10; the body force
+    // bound takes |g| plus the largest tank acceleration
     double gn = 0.0;
     for (int k = 0; k < 3; ++k) gn += d->g[k] * d->g[k];
-    gn = std::sqrt(gn);
+    const double w = 2.0 * M_PI * d->motion_freq;
+    gn = std::sqrt(gn) + std::sqrt(amp) * w * w;
     double dtmax = 0.25 * d->h / (1.1 * d->c0);
     if (gn > 0.0) dtmax = std::fmin(dtmax, 0.25 * std::sqrt(d->h / gn));
     if (d->dt > dtmax * 1.01) return SPH_ERR_CONFIG;  // 1 % slack: dt held fixed while c0 is varied
