@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-4m", action="store_true", help="skip the dx = 0.003 m (4M fluid) point")
     ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase dam break point")
     ap.add_argument("--no-sloshing", action="store_true", help="skip the shaken two-phase tank points")
+    ap.add_argument("--no-wedge", action="store_true", help="skip the dam break with a wedge point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
@@ -238,6 +239,22 @@ def main():
             del Ss
             torch.cuda.empty_cache()
 
+    # dam break with a wedge (Sec. 4.5) at the paper's dx = h_w/40: 5,721,296
+    # particles (the paper's run: 5,734,250)
+    wedge = None
+    if not args.no_wedge:
+        scw = scenes.dam_break_wedge(res=40, steps=args.steps)
+        kw = max(10, args.steps // 2)
+        Sw, wallw, stagew = timed_run(solver, scw, "f32", kw, max(2, args.warmup // 2))
+        nwt = scw.n_fluid + scw.n_wall
+        wedge = dict(workload=f"3-D dam break with a pi/3 wedge, h_w = 5.5 m, dx = h_w/40: {scw.n_fluid} fluid + "
+                              f"{scw.n_wall} wall ({scw.meta['n_wedge_wall']} on the wedge)",
+                     value=nwt * kw / wallw, ms_per_step=1e3 * wallw / kw, steps=kw,
+                     stage_ms={k: round(v, 4) for k, v in stagew.items()}, status=Sw.status())
+        print(f"[bench] wedge f32 {wedge['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        del Sw
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.no_fp64:
         k64 = args.fp64_steps or args.steps
@@ -309,6 +326,7 @@ def main():
         "fp32_4M": m4,
         "fp32_two_phase": tp,
         "fp32_sloshing": slosh,
+        "fp32_wedge": wedge,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
         "adjoint_fwd_ratio": adj["ratio"] if adj else None,

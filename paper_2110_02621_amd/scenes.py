@@ -397,6 +397,83 @@ def sloshing_tank(dim=3, dx=0.01, two_phase=True, amp=SLOSH_A0, freq=SLOSH_F0, l
                  motion_amp=tuple(amp_v), motion_freq=float(freq), **extra)
 
 
+WEDGE_H = 5.5  # wedge height h_w (Sec. 4.5)
+
+
+def wedge_walls(dx, n_in, x_apex, h_w, angle=math.pi / 3, layers=4):
+    """Wall dummies of a wedge on the floor: a prism across the tank width
+    (axis y in 3-D) whose cross-section is the isosceles triangle with apex
+    (x_apex, h_w) of opening ``angle`` and base on the floor z = 0.  The
+    dummies are the lattice points (i + 1/2) dx inside it within ``layers``
+    dx of a sloped face (the base sits on the tank floor)."""
+    dim = len(n_in) + 1
+    half = 0.5 * angle
+    b2 = h_w * math.tan(half)  # half base width
+    nzw = int(math.ceil(h_w / dx))
+    ix = np.arange(int(math.floor((x_apex - b2) / dx)) - 1, int(math.ceil((x_apex + b2) / dx)) + 1)
+    iz = np.arange(0, nzw)
+    axes = [ix] + ([np.arange(n_in[1])] if dim == 3 else []) + [iz]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")
+    ijk = np.stack([g.ravel() for g in grids[::-1]], axis=1)
+    p = (ijk.astype(np.float64) + 0.5) * dx
+    x, z = p[:, 0], p[:, dim - 1]
+    c, s = math.cos(half), math.sin(half)
+    # distances inside the two sloped faces (outward normals (-c, s), (c, s))
+    dl = c * (x - (x_apex - b2)) - s * z
+    dr = c * ((x_apex + b2) - x) - s * z
+    depth = np.minimum(dl, dr)
+    keep = (depth >= 0.0) & (depth < layers * dx)
+    return p[keep]
+
+
+def dam_break_wedge(res=40, h_w=WEDGE_H, tank=(16.0, 5.5, 3.0), column=(6.0, 2.0), layers=4,
+                    mu=0.0, steps=1000, penalty_all=True, dim=3):
+    """Dam break with a wedge (Sec. 4.5): dx = h_w / res, a pi/3 wedge of
+    height h_w across the whole width on the middle of the downstream bed.
+    Tank length x width x side height and the water column's length x height
+    are in units of h_w (the paper's tank was in a figure; these sizes give
+    about its 5,734,250 particles at res = 40).  ``layers`` rows of wall
+    dummies on the floor and the sides, open top.  dim = 2 drops the width."""
+    dx = h_w / res
+    n = lambda v: int(round(v * h_w / dx))
+    nx, ny, nz = n(tank[0]), n(tank[1]), n(tank[2])
+    ncx, ncz = n(column[0]), n(column[1])
+    H = ncz * dx
+    horiz = [nx, ny] if dim == 3 else [nx]
+    fx = _lattice([ncx] + horiz[1:] + [ncz], dx)
+    x_apex = (ncx + (nx - ncx) // 2) * dx  # a lattice face: the wedge is mirror-symmetric on the lattice
+    wt = tank_walls(dim, horiz, nz, dx, layers=layers)
+    ww = wedge_walls(dx, horiz, x_apex, h_w, layers=layers)
+    wx = np.concatenate([wt, ww])
+    h = H_OVER_DX * dx
+    c0 = sound_speed(H)
+    rho = _hydrostatic_rho(fx[:, dim - 1], H, RHO_WATER, c0)
+    pad = (layers + 0.5) * dx
+    top = [nx * dx + pad] + ([ny * dx + pad] if dim == 3 else []) + [nz * dx + 0.5 * H]
+    lo, hi = _box([-pad] * dim, top)
+    g = np.zeros(3)
+    g[dim - 1] = -G
+    return Scene(f"dam_break_wedge_{dim}d", dim, dx, h, RHO_WATER, c0, mu, 1.0, g,
+                 time_step(h, c0), steps, H, fx, np.zeros_like(fx), rho, wx, lo, hi,
+                 penalty_all=penalty_all,
+                 meta=dict(h_w=h_w, x_apex=x_apex, angle=math.pi / 3, n_tank_wall=int(len(wt)),
+                           n_wedge_wall=int(len(ww)), layers=layers, tank_l=nx * dx,
+                           tank_w=(ny * dx if dim == 3 else None)))
+
+
+def inside_wedge(sc, x):
+    """True for points strictly inside the wedge solid of a wedge scene."""
+    x = np.asarray(x, dtype=np.float64)
+    half = 0.5 * sc.meta["angle"]
+    xa, hw = sc.meta["x_apex"], sc.meta["h_w"]
+    b2 = hw * math.tan(half)
+    c, s_ = math.cos(half), math.sin(half)
+    z = x[:, sc.dim - 1]
+    dl = c * (x[:, 0] - (xa - b2)) - s_ * z
+    dr = c * ((xa + b2) - x[:, 0]) - s_ * z
+    return (dl > 0) & (dr > 0) & (z > 0)
+
+
 def by_name(name: str, **kw) -> Scene:
     table = {
         "hydrostatic_tank_2d": hydrostatic_tank_2d,
@@ -408,5 +485,6 @@ def by_name(name: str, **kw) -> Scene:
         "two_phase_tank_2d": two_phase_tank_2d,
         "dam_break_3d_two_phase": dam_break_3d_two_phase,
         "sloshing_tank": sloshing_tank,
+        "dam_break_wedge": dam_break_wedge,
     }
     return table[name](**kw)

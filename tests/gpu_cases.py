@@ -55,6 +55,9 @@ def small_scenes():
         "box3d": lambda: scenes.random_box(dim=3, n=3000, seed=1),
         "dam3d": lambda: scenes.dam_break_3d(dx=0.03, steps=100),
         "dam2d": lambda: scenes.dam_break_2d(dx=0.04, steps=100),
+        # the wedge of Sec. 4.5 (sharp corners: Eq. (16) normals, penalty)
+        "wedge3d": lambda: scenes.dam_break_wedge(res=6, dim=3, tank=(16.0, 1.0, 3.0)),
+        "wedge2d": lambda: scenes.dam_break_wedge(res=10, dim=2),
     }
 
 

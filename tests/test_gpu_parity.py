@@ -37,7 +37,7 @@ def by_pid(raw_pid, values):
 
 # ---------------------------------------------------------------- sort + pairs
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "near2d", "near3d"])
+@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "wedge3d", "near2d", "near3d"])
 def test_pair_sets_and_sort_bitexact(solver_mod, name, prec):
     sc = near_cutoff_scene(int(name[-2])) if name.startswith("near") else SMALL[name]()
     print(f"[pairs] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
@@ -82,7 +82,7 @@ def test_pair_sets_and_sort_bitexact(solver_mod, name, prec):
 
 # ---------------------------------------------------------------- one step, stage by stage
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "dam2d"])
+@pytest.mark.parametrize("name", ["box2d", "box3d", "dam3d", "dam2d", "wedge3d", "wedge2d"])
 def test_stage_parity(solver_mod, name, prec):
     sc = SMALL[name]()
     print(f"[stage] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
@@ -161,7 +161,7 @@ def test_stage_parity(solver_mod, name, prec):
 
 # ---------------------------------------------------------------- trajectories
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("name", ["dam3d", "dam2d"])
+@pytest.mark.parametrize("name", ["dam3d", "dam2d", "wedge3d", "wedge2d"])
 def test_trajectory_steps_1_10_100(solver_mod, name, prec):
     sc = SMALL[name]()
     print(f"[traj] {name} {prec} nf={sc.n_fluid} nw={sc.n_wall}", flush=True)
@@ -376,7 +376,7 @@ def test_full_size_sampled_parity(solver_mod, name):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("name", ["box3d", "dam3d", "dam2d"])
+@pytest.mark.parametrize("name", ["box3d", "dam3d", "dam2d", "wedge3d"])
 def test_lists_and_cell_walk_agree_bitwise(solver_mod, name, prec):
     # The sweeps read neighbour masks when present and walk the cells
     # otherwise: same pairs, same order, same arithmetic, same bits.
