@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase dam break point")
     ap.add_argument("--no-sloshing", action="store_true", help="skip the shaken two-phase tank points")
     ap.add_argument("--no-wedge", action="store_true", help="skip the dam break with a wedge point")
+    ap.add_argument("--sloshing-only", type=float, default=None, metavar="DX",
+                    help="time only the shaken two-phase tank at this dx (kernel profiles of that case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
@@ -147,6 +149,18 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2110_02621_amd import scenes, solver
+
+    if args.sloshing_only:
+        scs = scenes.sloshing_tank(dim=3, dx=args.sloshing_only, steps=args.steps)
+        Ss, walls_, stages = timed_run(solver, scs, "f32", args.steps, args.warmup)
+        ns = scs.n_fluid + scs.n_wall
+        print(json.dumps(dict(workload=f"3-D two-phase sloshing tank, dx={args.sloshing_only} m: {scs.n_heavy} water "
+                                       f"+ {scs.n_fluid - scs.n_heavy} air + {scs.n_wall} wall",
+                              value=ns * args.steps / walls_, unit="particle-steps/s",
+                              ms_per_step=1e3 * walls_ / args.steps, steps=args.steps,
+                              stage_ms={k: round(v, 4) for k, v in stages.items()}, status=Ss.status())),
+              flush=True)
+        return
 
     sc = scenes.dam_break_3d(dx=args.dx, obstacles=args.obstacles, seed=0, steps=args.steps)
     nf, nw = sc.n_fluid, sc.n_wall

@@ -177,20 +177,22 @@ __global__ void __launch_bounds__(kBlock) k_place(const int32_t* __restrict__ ke
     if (i < n) perm[start[key[i]] + slot[i]] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(kBlock) k_cellsort(const int32_t* __restrict__ start,
-                                                      int64_t ncell, int32_t* __restrict__ perm) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
+// In-cell order by source index: each entry's rank among the entries of its
+// cell (the sources are distinct), so the permutation is that of a stable
+// counting sort whatever order the histogram atomics handed out slots in.
+// One thread per entry; the cell's few entries are read from cache.
+__global__ void __launch_bounds__(kBlock) k_cellrank(const int32_t* __restrict__ key,
+                                                      const int32_t* __restrict__ start,
+                                                      const int32_t* __restrict__ placed, int64_t n,
+                                                      int32_t* __restrict__ perm) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int v = placed[p];
+    const int c = key[v];
     const int a = start[c], b = start[c + 1];
-    for (int i = a + 1; i < b; ++i) {
-        const int v = perm[i];
-        int j = i - 1;
-        while (j >= a && perm[j] > v) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = v;
-    }
+    int r = 0;
+    for (int q = a; q < b; ++q) r += placed[q] < v ? 1 : 0;
+    perm[a + r] = v;
 }
 
 template <typename T, int D>
@@ -994,13 +996,15 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 
 // Sort n keys into cell order: start table + permutation (scratch.perm).
+// The histogram's slot of each key goes to scratch.perm, the placement by
+// slot to scratch.slot, and the in-cell ranking back to scratch.perm.
 int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n, int32_t* start,
               hipStream_t st) {
     const int64_t nc = d->n_cells;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nc)), dim3(kBlock), 0, st, s.count, nc, 0);
     SPH_LAUNCH_CHECK();
     if (n > 0) {
-        hipLaunchKernelGGL(k_hist, dim3(grid_for(n)), dim3(kBlock), 0, st, key, n, s.count, s.slot);
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(n)), dim3(kBlock), 0, st, key, n, s.count, s.perm);
         SPH_LAUNCH_CHECK();
     }
     const int ntiles = (int)((nc + kScanTile - 1) / kScanTile);
@@ -1012,10 +1016,10 @@ int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n
                        start, (int32_t)n);
     SPH_LAUNCH_CHECK();
     if (n > 0) {
-        hipLaunchKernelGGL(k_place, dim3(grid_for(n)), dim3(kBlock), 0, st, key, s.slot, n, start,
-                           s.perm);
+        hipLaunchKernelGGL(k_place, dim3(grid_for(n)), dim3(kBlock), 0, st, key, s.perm, n, start,
+                           s.slot);
         SPH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cellsort, dim3(grid_for(nc)), dim3(kBlock), 0, st, start, nc, s.perm);
+        hipLaunchKernelGGL(k_cellrank, dim3(grid_for(n)), dim3(kBlock), 0, st, key, start, s.slot, n, s.perm);
         SPH_LAUNCH_CHECK();
     }
     return SPH_OK;
