@@ -285,35 +285,49 @@ struct NbrMask {
     int64_t n;
 };
 
-// Pair bits of candidates [ja, jb) of row R into one mask word whose bit 0
-// is candidate wbase (jb - wbase <= 64): bit j - wbase is set when j is a
-// neighbour.  get(j) returns j's position record.
+// Pair bits of candidates [ja, jb) of one cell of a row into one mask word
+// whose bit 0 is candidate wbase (jb - wbase <= 64): bit j - wbase is set
+// when j is a neighbour.  sx is the cell's x shift (what row_shift gives for
+// every j of the cell), so the distance is the same arithmetic as the
+// walk's.  get(j) returns j's position record.
 template <typename T, int D, typename Get>
-__device__ __forceinline__ uint64_t row_bits(const Par<T>& P, const Row& R, int ja, int jb, int wbase,
-                                             const T oi[3], T sy, T sz, Get&& get) {
+__device__ __forceinline__ uint64_t cell_bits(const Par<T>& P, int ja, int jb, int wbase, T sx, const T oi[3],
+                                              T sy, T sz, Get&& get) {
     uint64_t m = 0;
     if (ja >= jb) return m;
     uint64_t bit = 1ull << (ja - wbase);
     for (int j = ja; j < jb; ++j) {
         const Rec<T> q = get(j);
         T d[3];
-        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, sx, sy, sz, d);
         m |= r2 < P.rc2 ? bit : 0ull;
         bit <<= 1;
     }
     return m;
 }
 
-// Both words of row R (candidates past base + 128 are not recorded; the
-// caller flags the row as overflowing).
+// Candidates [ja, jb) of one cell of row R into the row's two words.
+template <typename T, int D, typename Get>
+__device__ __forceinline__ void cell_words(const Par<T>& P, const Row& R, int ja, int jb, T sx, const T oi[3],
+                                           T sy, T sz, Get&& get, uint64_t& m0, uint64_t& m1) {
+    const int split = R.base + 64;
+    m0 |= cell_bits<T, D>(P, ja, jb < split ? jb : split, R.base, sx, oi, sy, sz, get);
+    if (jb > split)
+        m1 |= cell_bits<T, D>(P, ja > split ? ja : split, jb < split + 64 ? jb : split + 64, split, sx, oi, sy,
+                              sz, get);
+}
+
+// Both words of row R, cell by cell (left, own, right), each with its
+// constant x shift; candidates past base + 128 are not recorded (the caller
+// flags the row as overflowing).
 template <typename T, int D, typename Get>
 __device__ __forceinline__ void row_words(const Par<T>& P, const Row& R, const T oi[3], T sy, T sz, Get&& get,
                                           uint64_t& m0, uint64_t& m1) {
-    const int split = R.base + 64;
-    m0 = row_bits<T, D>(P, R, R.j0, R.j1 < split ? R.j1 : split, R.base, oi, sy, sz, get);
-    m1 = R.j1 > split ? row_bits<T, D>(P, R, R.j0 > split ? R.j0 : split, R.j1 < split + 64 ? R.j1 : split + 64,
-                                       split, oi, sy, sz, get)
-                      : 0ull;
+    m0 = 0;
+    m1 = 0;
+    cell_words<T, D>(P, R, R.j0, R.jm, -P.L, oi, sy, sz, get, m0, m1);
+    cell_words<T, D>(P, R, R.jm, R.jp, T(0), oi, sy, sz, get, m0, m1);
+    cell_words<T, D>(P, R, R.jp, R.j1, P.L, oi, sy, sz, get, m0, m1);
 }
 
 // Build the masks of query i (rows kept by the walk only).  Returns the
