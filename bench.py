@@ -54,7 +54,7 @@ DENSITY_BYTES_PARTICLE = 88
 # kernel sources whose SHA-256 is recorded; once those change the traffic is
 # reported as null until the counters are taken again.
 TRAFFIC = {
-    "sources_sha256": "9b481c710fa420b335b3a69a9cf87c1bb9989f11b6c3eb665fd23a38d2219a8c",
+    "sources_sha256": "1e340e276a71f84149ed016811dc1da651b53adbe171b6fbf1325ae43af725da",
     "momentum": 1709.8e6 + 269.2e6,
     "continuity": 1645.3e6 + 139.6e6,
 }

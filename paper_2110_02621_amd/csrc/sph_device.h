@@ -584,8 +584,9 @@ __device__ __forceinline__ int64_t regroup_block(const Par<T>& P, const Rec<T>* 
     return blk0 + perm[t];
 }
 
-// The mask builder with LDS-staged candidate rows (positions only), for a
-// wave in one row of cells; same results as build_mask.
+// The mask builder with LDS-staged candidate rows (the union of the wave's
+// row ranges, position records), for a wave in one row of cells; same
+// results as build_mask.
 template <typename T, int D, int CAP>
 __device__ __forceinline__ int build_mask_staged(const Par<T>& P, const int32_t* __restrict__ start,
                                                  const Rec<T>* __restrict__ pk, SPH_LDS Rec<T>* sp, const WaveSpan& S,

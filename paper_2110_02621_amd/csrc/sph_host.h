@@ -144,9 +144,9 @@ struct Scratch {
     double* part;     // diag partials
     void* sig;        // n_fluid T: sigma summed by the last momentum sweep
     // packed copies of the sorted state that the sweeps gather from
-    // (Rec<T> = 4 T): pk[s] = (offset, rho[s] - rho0), vk[s] = (vel[s], 0)
-    // mirror the two density and velocity copies; wk = (wall offset, p_w),
-    // nk = (wall normal, 0)
+    // (Rec<T> = 4 T): pk[s] = (offset, rho[s] - rho0), vk[s] = (vel[s],
+    // the particle's reference density) mirror the two density and
+    // velocity copies; wk = (wall offset, p_w), nk = (wall normal, 0)
     void* pk[2];
     void* vk[2];
     void* wk;

@@ -55,8 +55,9 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 //      cell is exact; the slot order inside a cell is arbitrary);
 //   2. exclusive scan of the counts -> cell start table;
 //   3. place: perm[start[key_i] + slot_i] = i;
-//   4. per-cell insertion sort of perm by source index, which makes the
-//      order inside a cell the prior order: deterministic and stable;
+//   4. rank of each entry among its cell's entries by source index, which
+//      makes the order inside a cell the prior order: deterministic and
+//      stable;
 //   5. gather of every field through perm.
 // ---------------------------------------------------------------------------
 
