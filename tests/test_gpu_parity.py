@@ -311,6 +311,8 @@ def test_edge_coincident_particles(solver_mod):
 FULL = {
     "dam3d_dx0.004": lambda: scenes.dam_break_3d(dx=0.004),
     "dam3d_obst_dx0.0025": lambda: scenes.dam_break_3d(dx=0.0025, obstacles=8, seed=0),
+    # the dam break with a wedge at the paper's dx = h_w/40 (5,721,296 particles)
+    "wedge3d_res40": lambda: scenes.dam_break_wedge(res=40),
 }
 
 
