@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--sloshing-only", type=float, default=None, metavar="DX",
                     help="time only the shaken two-phase tank at this dx (kernel profiles of that case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps of the CPU baseline (about 3 s each)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--adj-steps", type=int, default=1000, help="steps of the differentiable 2-D dam break")
     ap.add_argument("--adj-dx", type=float, default=0.005)
