@@ -289,19 +289,23 @@ struct NbrMask {
 // whose bit 0 is candidate wbase (jb - wbase <= 64): bit j - wbase is set
 // when j is a neighbour.  sx is the cell's x shift (what row_shift gives for
 // every j of the cell), so the distance is the same arithmetic as the
-// walk's.  get(j) returns j's position record.
+// walk's.  get(j) returns j's position record.  The candidates are tested
+// in chunks of up to 32, each from its last candidate down, shifting the
+// results into a 32-bit word that is then placed at the chunk's offset.
 template <typename T, int D, typename Get>
 __device__ __forceinline__ uint64_t cell_bits(const Par<T>& P, int ja, int jb, int wbase, T sx, const T oi[3],
                                               T sy, T sz, Get&& get) {
     uint64_t m = 0;
-    if (ja >= jb) return m;
-    uint64_t bit = 1ull << (ja - wbase);
-    for (int j = ja; j < jb; ++j) {
-        const Rec<T> q = get(j);
-        T d[3];
-        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, sx, sy, sz, d);
-        m |= r2 < P.rc2 ? bit : 0ull;
-        bit <<= 1;
+    for (int c0 = ja; c0 < jb; c0 += 32) {
+        const int c1 = jb - c0 < 32 ? jb : c0 + 32;
+        uint32_t w = 0;
+        for (int j = c1 - 1; j >= c0; --j) {  // bit j - c0 of w once the chunk is done
+            const Rec<T> q = get(j);
+            T d[3];
+            const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, sx, sy, sz, d);
+            w = (w << 1) | (r2 < P.rc2 ? 1u : 0u);
+        }
+        m |= (uint64_t)w << (c0 - wbase);
     }
     return m;
 }
