@@ -299,7 +299,15 @@ __device__ __forceinline__ uint64_t cell_bits(const Par<T>& P, int ja, int jb, i
     for (int c0 = ja; c0 < jb; c0 += 32) {
         const int c1 = jb - c0 < 32 ? jb : c0 + 32;
         uint32_t w = 0;
-        for (int j = c1 - 1; j >= c0; --j) {  // bit j - c0 of w once the chunk is done
+        int j = c1 - 1;
+        for (; j > c0; j -= 2) {  // two at a time: bit j - c0 of w once the chunk is done
+            const Rec<T> qb = get(j - 1), qa = get(j);
+            T d[3];
+            const T ra = rel2<T, D>(oi, qa.x, qa.y, qa.z, sx, sy, sz, d);
+            const T rb = rel2<T, D>(oi, qb.x, qb.y, qb.z, sx, sy, sz, d);
+            w = (w << 2) | (ra < P.rc2 ? 2u : 0u) | (rb < P.rc2 ? 1u : 0u);
+        }
+        if (j == c0) {
             const Rec<T> q = get(j);
             T d[3];
             const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, sx, sy, sz, d);
