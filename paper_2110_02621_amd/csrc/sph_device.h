@@ -300,14 +300,17 @@ __device__ __forceinline__ uint64_t cell_bits(const Par<T>& P, int ja, int jb, i
         const int c1 = jb - c0 < 32 ? jb : c0 + 32;
         uint32_t w = 0;
         int j = c1 - 1;
-        for (; j > c0; j -= 2) {  // two at a time: bit j - c0 of w once the chunk is done
-            const Rec<T> qb = get(j - 1), qa = get(j);
+        for (; j > c0 + 2; j -= 4) {  // four at a time: bit j - c0 of w once the chunk is done
+            const Rec<T> q0 = get(j - 3), q1 = get(j - 2), q2 = get(j - 1), q3 = get(j);
             T d[3];
-            const T ra = rel2<T, D>(oi, qa.x, qa.y, qa.z, sx, sy, sz, d);
-            const T rb = rel2<T, D>(oi, qb.x, qb.y, qb.z, sx, sy, sz, d);
-            w = (w << 2) | (ra < P.rc2 ? 2u : 0u) | (rb < P.rc2 ? 1u : 0u);
+            const T r0 = rel2<T, D>(oi, q0.x, q0.y, q0.z, sx, sy, sz, d);
+            const T r1 = rel2<T, D>(oi, q1.x, q1.y, q1.z, sx, sy, sz, d);
+            const T r2 = rel2<T, D>(oi, q2.x, q2.y, q2.z, sx, sy, sz, d);
+            const T r3 = rel2<T, D>(oi, q3.x, q3.y, q3.z, sx, sy, sz, d);
+            w = (w << 4) | (r3 < P.rc2 ? 8u : 0u) | (r2 < P.rc2 ? 4u : 0u) | (r1 < P.rc2 ? 2u : 0u) |
+                (r0 < P.rc2 ? 1u : 0u);
         }
-        if (j == c0) {
+        for (; j >= c0; --j) {
             const Rec<T> q = get(j);
             T d[3];
             const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, sx, sy, sz, d);
