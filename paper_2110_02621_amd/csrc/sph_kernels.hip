@@ -599,7 +599,9 @@ __global__ void __launch_bounds__(kBlock)
     T sig = T(0), comp = T(0);  // two phases: sigma at these positions for the light phase
     auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
         if (MP) kahan_add(sig, comp, wendland_W(P, root(r2)));
-        if (!(r2 > T(0))) return;
+        // no branch for r = 0 (the particle itself, or a coincident one):
+        // every part of its term carries r or d, so it adds an exact zero,
+        // and the velocity record is read without waiting on r2
         const T r = root(r2);
         const T F = wendland_F(P, r);
         const T drj = q.w;
@@ -686,8 +688,11 @@ __global__ void __launch_bounds__(kBlock)
     T s = T(0), comp = T(0);
     auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
         kahan_add(s, comp, wendland_W(P, root(r2)));
-        if (!(r2 > T(0))) return;
-        const T rinv = rsq(r2);
+        // no branch for r = 0 (the particle itself, or a coincident one): with
+        // the reciprocal root taken of 1 there, every part of its force carries
+        // r or d and adds an exact zero, and the velocity record is read
+        // without waiting on r2
+        const T rinv = rsq(r2 > T(0) ? r2 : T(1));
         const T r = r2 * rinv;
         const T F = wendland_F(P, r);
         const T drj = q.w;
