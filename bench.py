@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase dam break point")
     ap.add_argument("--no-sloshing", action="store_true", help="skip the shaken two-phase tank points")
     ap.add_argument("--no-wedge", action="store_true", help="skip the dam break with a wedge point")
+    ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint/forward ratio")
     ap.add_argument("--sloshing-only", type=float, default=None, metavar="DX",
                     help="time only the shaken two-phase tank at this dx (kernel profiles of that case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -149,6 +150,16 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2110_02621_amd import scenes, solver
+
+    if args.adjoint_only:
+        from paper_2110_02621_amd import adjoint
+        sca = scenes.dam_break_2d(dx=args.adj_dx, steps=args.adj_steps)
+        adjoint.probe_gradient(scenes.dam_break_2d(dx=args.adj_dx, steps=2 * args.adj_K),
+                               precision="f32", K=args.adj_K)  # warm-up
+        r = adjoint.probe_gradient(sca, precision="f32", K=args.adj_K, return_timings=True)
+        print(json.dumps(dict(t_forward_s=r["t_forward"], t_backward_s=r["t_backward"],
+                              ratio=r["t_backward"] / r["t_forward"], grad=r["grad"])), flush=True)
+        return
 
     if args.sloshing_only:
         scs = scenes.sloshing_tank(dim=3, dx=args.sloshing_only, steps=args.steps)

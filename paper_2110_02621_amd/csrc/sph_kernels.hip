@@ -1228,12 +1228,32 @@ int step_t(const sph_desc* d, sph_buffers* b, int nsteps, hipStream_t st) {
     return SPH_OK;
 }
 
-// Device-to-device copy of n bytes (skipped when either side is absent).
-inline int copy_d2d(const void* dst, const void* src, size_t n, hipStream_t st) {
-    if (!dst || !src || n == 0) return SPH_OK;
-    return hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyDeviceToDevice, st) == hipSuccess
-               ? SPH_OK
-               : SPH_ERR_LAUNCH;
+// Up to kMaxCopies device-to-device copies of 4-byte words in one launch
+// (blockIdx.y picks the copy).
+constexpr int kMaxCopies = 16;
+struct CopyList {
+    const uint32_t* src[kMaxCopies];
+    uint32_t* dst[kMaxCopies];
+    int64_t words[kMaxCopies];
+};
+
+__global__ void __launch_bounds__(kBlock) k_copy_words(CopyList L) {
+    const int c = blockIdx.y;
+    const int64_t n = L.words[c];
+    const uint32_t* __restrict__ src = L.src[c];
+    uint32_t* __restrict__ dst = L.dst[c];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+// Adds a copy of n bytes (a multiple of 4) to the list, skipped when either
+// side is absent or n is 0.
+inline void add_copy(CopyList& L, int& m, const void* dst, const void* src, size_t n) {
+    if (!dst || !src || n == 0) return;
+    L.src[m] = (const uint32_t*)src;
+    L.dst[m] = (uint32_t*)dst;
+    L.words[m] = (int64_t)(n / 4);
+    ++m;
 }
 
 template <typename T, int D>
@@ -1246,28 +1266,43 @@ int step_frame_t(const sph_desc* d, sph_buffers* b, void* sigma_cur, sph_frame* 
     b->sigma_out = keep;
     if (!rc) rc = build_cells_t<T, D>(d, b, st);
     if (rc) return rc;
-    const size_t rows = d->dim == 3 ? 9 : 3;
-    rc = copy_d2d(nx->key, b->key[0], 4 * (size_t)nf, st);
-    if (!rc) rc = copy_d2d(nx->pid, b->pid[0], 4 * (size_t)nf, st);
-    if (!rc) rc = copy_d2d(nx->off, b->off[0], ts * D * (size_t)nf, st);
-    if (!rc) rc = copy_d2d(nx->fstart, b->fstart, 4 * (size_t)(d->n_cells + 1), st);
-    if (!rc) rc = copy_d2d(nx->vh, b->vel[b->sel_vel], ts * D * (size_t)nf, st);
-    if (!rc) rc = copy_d2d(nx->rt, b->rho[b->sel_rho], ts * (size_t)nf, st);
-    if (!rc && b->nbr_ff && nx->nbr_ff && nx->nbr_fw && nx->nbr_wf && nx->cnt_ff && nx->cnt_fw && nx->cnt_wf) {
-        const size_t wf = 8 * 2 * rows * (size_t)nf, ww = 8 * 2 * rows * (size_t)nw;
-        rc = copy_d2d(nx->nbr_ff, b->nbr_ff, wf, st);
-        if (!rc) rc = copy_d2d(nx->nbr_fw, b->nbr_fw, wf, st);
-        if (!rc) rc = copy_d2d(nx->nbr_wf, b->nbr_wf, ww, st);
-        if (!rc) rc = copy_d2d(nx->cnt_ff, b->cnt_ff, 4 * (size_t)nf, st);
-        if (!rc) rc = copy_d2d(nx->cnt_fw, b->cnt_fw, 4 * (size_t)nf, st);
-        if (!rc) rc = copy_d2d(nx->cnt_wf, b->cnt_wf, 4 * (size_t)nw, st);
-    }
+    // Every array the frame records stays as it is from here to the end of
+    // the step (the sweeps write the other velocity and density copies), so
+    // all of them are copied in one launch at the end.
+    const void* vh = b->vel[b->sel_vel];
+    const void* rt = b->rho[b->sel_rho];
     if (!rc) rc = wall_bc_t<T, D>(d, b, st);
-    if (!rc) rc = copy_d2d(nx->pw, b->pw, ts * (size_t)nw, st);
     if (!rc) rc = forces_t<T, D>(d, b, SPH_CONTINUITY, st);
-    if (!rc) rc = copy_d2d(nx->rho, b->rho[b->sel_rho], ts * (size_t)nf, st);
+    const void* rho1 = b->rho[b->sel_rho];
     if (!rc) rc = forces_t<T, D>(d, b, SPH_MOMENTUM, st);
     if (rc) return rc;
+    CopyList L;
+    int m = 0;
+    add_copy(L, m, nx->key, b->key[0], 4 * (size_t)nf);
+    add_copy(L, m, nx->pid, b->pid[0], 4 * (size_t)nf);
+    add_copy(L, m, nx->off, b->off[0], ts * D * (size_t)nf);
+    add_copy(L, m, nx->fstart, b->fstart, 4 * (size_t)(d->n_cells + 1));
+    add_copy(L, m, nx->vh, vh, ts * D * (size_t)nf);
+    add_copy(L, m, nx->rt, rt, ts * (size_t)nf);
+    add_copy(L, m, nx->pw, b->pw, ts * (size_t)nw);
+    add_copy(L, m, nx->rho, rho1, ts * (size_t)nf);
+    if (b->nbr_ff && nx->nbr_ff && nx->nbr_fw && nx->nbr_wf && nx->cnt_ff && nx->cnt_fw && nx->cnt_wf) {
+        const size_t rows = d->dim == 3 ? 9 : 3;
+        const size_t wf = 8 * 2 * rows * (size_t)nf, ww = 8 * 2 * rows * (size_t)nw;
+        add_copy(L, m, nx->nbr_ff, b->nbr_ff, wf);
+        add_copy(L, m, nx->nbr_fw, b->nbr_fw, wf);
+        add_copy(L, m, nx->nbr_wf, b->nbr_wf, ww);
+        add_copy(L, m, nx->cnt_ff, b->cnt_ff, 4 * (size_t)nf);
+        add_copy(L, m, nx->cnt_fw, b->cnt_fw, 4 * (size_t)nf);
+        add_copy(L, m, nx->cnt_wf, b->cnt_wf, 4 * (size_t)nw);
+    }
+    if (m > 0) {
+        int64_t most = 0;
+        for (int k = 0; k < m; ++k) most = L.words[k] > most ? L.words[k] : most;
+        const int gx = (int)((most + kBlock - 1) / kBlock < 2048 ? (most + kBlock - 1) / kBlock : 2048);
+        hipLaunchKernelGGL(k_copy_words, dim3(gx > 0 ? gx : 1, m), dim3(kBlock), 0, st, L);
+        SPH_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, st, b->diag);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
