@@ -117,6 +117,17 @@ __device__ __forceinline__ void block_partials(const double v[kNth], double* par
     if (threadIdx.x < kNth) part[(int64_t)blockIdx.x * kNth + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Abar = ab + ha vb of every particle in a frame's sorted order (the pair
+// sweeps read it by neighbour index).
+__global__ void __launch_bounds__(kBlock)
+    k_gather_abar(int dim, int64_t nf, const int32_t* __restrict__ pid, const double* __restrict__ ab,
+                  const double* __restrict__ vb, double ha, double* __restrict__ abar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int64_t p = pid[i];
+    for (int k = 0; k < dim; ++k) abar[k * nf + i] = ab[k * nf + p] + (vb ? ha * vb[k * nf + p] : 0.0);
+}
+
 __global__ void k_theta_reduce(const double* __restrict__ part, int nblocks, double* __restrict__ theta) {
     __shared__ double red[kNth][kBlock];
     double v[kNth] = {0, 0, 0, 0};
@@ -160,9 +171,9 @@ __global__ void __launch_bounds__(kBlock)
               const T* __restrict__ rp, const int32_t* __restrict__ wkey,
               const T* __restrict__ woff, const int32_t* __restrict__ wstart,
               const T* __restrict__ pw, const T* __restrict__ nrm, const double* __restrict__ ab,
-              const double* __restrict__ vb, double ha, const double* __restrict__ rho_in,
-              double* __restrict__ xb, double* __restrict__ vh_out, double* __restrict__ rp_out,
-              double* __restrict__ part) {
+              const double* __restrict__ vb, double ha, const double* __restrict__ abar,
+              const double* __restrict__ rho_in, double* __restrict__ xb, double* __restrict__ vh_out,
+              double* __restrict__ rp_out, double* __restrict__ rp_out_s, double* __restrict__ part) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double th[kNth] = {0, 0, 0, 0};
     if (i < nf) {
@@ -182,11 +193,10 @@ __global__ void __launch_bounds__(kBlock)
                     [&](int j, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;
             const PairGeo G = geo<D>(Q, dT);
-            const int64_t pj = pid[j];
             double vj[3] = {0, 0, 0}, dA[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) {
                 vj[k] = (double)vh[k * nf + j];
-                dA[k] = Ai[k] - (ab[k * nf + pj] + (vb ? ha * vb[k * nf + pj] : 0.0));
+                dA[k] = Ai[k] - abar[k * nf + j];  // j's Abar, gathered into this frame's order
                 dv[k] = vi[k] - vj[k];
             }
             const double rj = Q.rho0 + (double)rp[j];
@@ -274,7 +284,9 @@ __global__ void __launch_bounds__(kBlock)
             xb[k * nf + p] += gx[k];
             vh_out[k * nf + p] = (vb ? vb[k * nf + p] : 0.0) + gv[k];
         }
-        rp_out[p] = (rho_in ? rho_in[p] : 0.0) + gr;
+        const double rpv = (rho_in ? rho_in[p] : 0.0) + gr;
+        rp_out[p] = rpv;
+        if (rp_out_s) rp_out_s[i] = rpv;
     }
     block_partials(th, part);
 }
@@ -291,8 +303,8 @@ __global__ void __launch_bounds__(kBlock)
                const int32_t* __restrict__ fstart, const T* __restrict__ vh,
                const T* __restrict__ rt, const T* __restrict__ woff,
                const int32_t* __restrict__ wstart, const T* __restrict__ pw,
-               const double* __restrict__ rpb, double* __restrict__ xb, double* __restrict__ vhb,
-               double* __restrict__ rtb, double* __restrict__ part) {
+               const double* __restrict__ rpb, const double* __restrict__ rpbs, double* __restrict__ xb,
+               double* __restrict__ vhb, double* __restrict__ rtb, double* __restrict__ part) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double th[kNth] = {0, 0, 0, 0};
     if (i < nf) {
@@ -310,9 +322,8 @@ __global__ void __launch_bounds__(kBlock)
                     [&](int j, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;
             const PairGeo G = geo<D>(Q, dT);
-            const int64_t pj = pid[j];
             const double rj = Q.rho0 + (double)rt[j];
-            const double psi_j = 2.0 * Q.m * Q.dt * rpb[pj] * rj;
+            const double psi_j = 2.0 * Q.m * Q.dt * rpbs[j] * rj;
             double dv[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) dv[k] = vi[k] - (double)vh[k * nf + j];
             const double u = dotv<D>(dv, G.d);
@@ -373,9 +384,8 @@ __global__ void __launch_bounds__(kBlock)
                const T* __restrict__ nrm, const T* __restrict__ pw, const int32_t* __restrict__ pid,
                const T* __restrict__ off, const int32_t* __restrict__ fstart,
                const T* __restrict__ vh, const T* __restrict__ rp, const T* __restrict__ rt,
-               const double* __restrict__ ab, const double* __restrict__ vb, double ha,
-               const double* __restrict__ rpb, const int32_t* __restrict__ probe, int np,
-               double* __restrict__ lam) {
+               const double* __restrict__ abar, const double* __restrict__ rpbs,
+               const int32_t* __restrict__ probe, int np, double* __restrict__ lam) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nw) return;
     int c[3];
@@ -393,16 +403,15 @@ __global__ void __launch_bounds__(kBlock)
             const PairGeo G0 = geo<D>(Q, dT);
             SW += G0.W;
             if (!(r2T > T(0))) return;
-            const int64_t pf = pid[f];
             double dfw[3] = {0, 0, 0}, vf[3] = {0, 0, 0};
             for (int k = 0; k < D; ++k) {
                 dfw[k] = -G0.d[k];
                 vf[k] = (double)vh[k * nf + f];
             }
             // momentum: fluid f sees this wall with p* of Eq. (11), viscous, penalty
-            if (ab) {
+            if (abar) {
                 double Af[3] = {0, 0, 0};
-                for (int k = 0; k < D; ++k) Af[k] = ab[k * nf + pf] + (vb ? ha * vb[k * nf + pf] : 0.0);
+                for (int k = 0; k < D; ++k) Af[k] = abar[k * nf + f];  // f's Abar in this frame's order
                 const double rf = Q.rho0 + (double)rp[f];
                 const double pf_ = Q.c2 * (double)rp[f];
                 const double Sw = rf + rw;
@@ -422,10 +431,10 @@ __global__ void __launch_bounds__(kBlock)
                 pbar += Cpw * Lin - 2.0 * C * a * pspw;
             }
             // continuity: psi_f G_fw with the reinitialised density
-            if (rpb) {
+            if (rpbs) {
                 const double rf = Q.rho0 + (double)rt[f];
                 const double pf_ = Q.c2 * (double)rt[f];
-                const double psi = 2.0 * Q.m * Q.dt * rpb[pf] * rf;
+                const double psi = 2.0 * Q.m * Q.dt * rpbs[f] * rf;
                 const double Sw = rf + rw;
                 const double uw = dotv<D>(vf, dfw);
                 const double E = rw * uw + (pf_ - pwv) * G0.r / Q.c;
@@ -497,7 +506,7 @@ __global__ void __launch_bounds__(kBlock)
                       const T* __restrict__ sigma, const T* __restrict__ rho,
                       const double* __restrict__ xb, const double* __restrict__ vhb,
                       const double* __restrict__ rtb, double* __restrict__ vb,
-                      double* __restrict__ ab, double* __restrict__ sigb, double* __restrict__ rhob) {
+                      double* __restrict__ ab, double* __restrict__ sigbs, double* __restrict__ rhob) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
     const int64_t p = pid[i];
@@ -515,7 +524,7 @@ __global__ void __launch_bounds__(kBlock)
     const double rs = Q.rho0 * (double)s / Q.sigma0;
     const double Rs = excess ? (Q.rho0 / Q.sigma0) * (1.0 - Q.rho0 / rstar) : Q.rho0 / Q.sigma0;
     const double Rr = excess ? Q.rho0 * rs / (rstar * rstar) : 0.0;
-    sigb[p] = Rs * rtb[p];
+    sigbs[i] = Rs * rtb[p];  // this frame's order: the number density sweep reads it by neighbour
     rhob[p] = Rr * rtb[p];
 }
 
@@ -525,7 +534,7 @@ __global__ void __launch_bounds__(kBlock)
     k_sigma_bwd(Par<T> P, AdjPar Q, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                 const int32_t* __restrict__ pid, const T* __restrict__ off,
                 const int32_t* __restrict__ fstart, const T* __restrict__ woff,
-                const int32_t* __restrict__ wstart, const double* __restrict__ sigb,
+                const int32_t* __restrict__ wstart, const double* __restrict__ sigbs,
                 double* __restrict__ xb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
@@ -533,13 +542,13 @@ __global__ void __launch_bounds__(kBlock)
     int c[3];
     cell_of(P, key[i], c);
     const T oi[3] = {off[i], off[nf + i], D == 3 ? off[2 * nf + i] : T(0)};
-    const double si = sigb[p];
+    const double si = sigbs[i];
     double gx[3] = {0, 0, 0};
     visit<T, D>(P, LF, i, fstart, off, off + nf, off + 2 * nf, c, oi,
                 [&](int j, const T dT[3], T r2T, uint32_t) {
         if (!(r2T > T(0))) return;
         const PairGeo G = geo<D>(Q, dT);
-        const double s = si + sigb[pid[j]];
+        const double s = si + sigbs[j];
         for (int k = 0; k < D; ++k) gx[k] += s * G.F * G.d[k];
     });
     if (nw > 0)
@@ -589,7 +598,9 @@ struct AdjWork {
     double* vhb;   // [dim][nf]
     double* rpb;   // [nf]
     double* rtb;   // [nf]
-    double* sigb;  // [nf]
+    double* sigb;  // [nf] number density adjoint, in the sorted order of the frame being reversed
+    double* abar;  // [dim][nf] Abar = ab + dt/2 vb, in the frame's sorted order
+    double* rpbs;  // [nf] rpb in the frame's sorted order
     double* lam;   // [nw]
     double* tmp;   // [dim][nf] discarded velocity adjoint of the initial state
     double* part;  // partial sums, kNth per block
@@ -610,6 +621,8 @@ AdjWork adj_layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
     w.rpb = take(sizeof(double) * (size_t)nf);
     w.rtb = take(sizeof(double) * (size_t)nf);
     w.sigb = take(sizeof(double) * (size_t)nf);
+    w.abar = take(sizeof(double) * d->dim * (size_t)nf);
+    w.rpbs = take(sizeof(double) * (size_t)nf);
     w.lam = take(sizeof(double) * (size_t)nw);
     w.tmp = take(sizeof(double) * d->dim * (size_t)nf);
     w.part = take(sizeof(double) * kNth * (size_t)((nmax + kBlock - 1) / kBlock + 1));
@@ -655,18 +668,21 @@ int forces_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, sp
     const AdjPar Q = make_adj(d);
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     const int nb = grid_for(nf);
+    hipLaunchKernelGGL(k_gather_abar, dim3(nb), dim3(kBlock), 0, st, D, nf, f->pid, a->ab, a->vb, Q.half_dt,
+                       w.abar);
+    SPH_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
                        fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, b->wkey,
                        (const T*)b->woff, b->wstart, (const T*)f->pw, (const T*)b->nrm, a->ab, a->vb,
-                       Q.half_dt, a->rhob, a->xb, w.vhb, w.rpb, w.part);
+                       Q.half_dt, (const double*)w.abar, a->rhob, a->xb, w.vhb, w.rpb, w.rpbs, w.part);
     SPH_LAUNCH_CHECK();
     int rc = reduce_theta(w, nb, a->theta, st);
     if (rc) return rc;
     hipLaunchKernelGGL((k_cont_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
                        fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rt, (const T*)b->woff,
-                       b->wstart, (const T*)f->pw, w.rpb, a->xb, w.vhb, w.rtb, w.part);
+                       b->wstart, (const T*)f->pw, w.rpb, (const double*)w.rpbs, a->xb, w.vhb, w.rtb, w.part);
     SPH_LAUNCH_CHECK();
     return reduce_theta(w, nb, a->theta, st);
 }
@@ -683,7 +699,7 @@ int wall_bc_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, s
                        fmask(f->nbr_wf, f->cnt_wf, nw), nf, nw,
                        b->wkey, b->wpid, (const T*)b->woff, (const T*)b->nrm, (const T*)f->pw, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, (const T*)f->rt,
-                       nf > 0 ? a->ab : nullptr, a->vb, Q.half_dt, nf > 0 ? w.rpb : nullptr,
+                       nf > 0 ? (const double*)w.abar : nullptr, nf > 0 ? (const double*)w.rpbs : nullptr,
                        b->n_probe > 0 ? b->probe : nullptr, b->n_probe, w.lam);
     SPH_LAUNCH_CHECK();
     if (nf == 0) return SPH_OK;
@@ -726,11 +742,15 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     const int nb = grid_for(nf);
     // a^0 = MOM(r^0, v^0, rho^0, p_w^0): Abar = ab (no kick), rho adjoint in place
+    hipLaunchKernelGGL(k_gather_abar, dim3(nb), dim3(kBlock), 0, st, D, nf, f->pid, a->ab, (const double*)nullptr,
+                       0.0, w.abar);
+    SPH_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_mom_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q, fmask(f->nbr_ff, f->cnt_ff, nf),
                        fmask(f->nbr_fw, f->cnt_fw, nf), nf, nw, f->key, f->pid,
                        (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho, b->wkey,
                        (const T*)b->woff, b->wstart, (const T*)f->pw, (const T*)b->nrm, a->ab,
-                       (const double*)nullptr, 0.0, a->rhob, a->xb, w.tmp, a->rhob, w.part);
+                       (const double*)nullptr, 0.0, (const double*)w.abar, a->rhob, a->xb, w.tmp, a->rhob,
+                       (double*)nullptr, w.part);
     SPH_LAUNCH_CHECK();
     int rc = reduce_theta(w, nb, a->theta, st);
     if (rc) return rc;
@@ -740,7 +760,7 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
                            fmask(f->nbr_wf, f->cnt_wf, nw), nf, nw,
                            b->wkey, b->wpid, (const T*)b->woff, (const T*)b->nrm, (const T*)f->pw, f->pid,
                            (const T*)f->off, f->fstart, (const T*)f->vh, (const T*)f->rho,
-                           (const T*)f->rho, a->ab, (const double*)nullptr, 0.0, (const double*)nullptr,
+                           (const T*)f->rho, (const double*)w.abar, (const double*)nullptr,
                            (const int32_t*)nullptr, 0, w.lam);
         SPH_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_pw_bwd<T, D>), dim3(nb), dim3(kBlock), 0, st, P, Q,
