@@ -198,6 +198,12 @@ def main():
         t = stage[k] * 1e-3
         kernels[k] = dict(ms=round(stage[k], 4), tflops=round(f / t / 1e12, 3),
                           alu_frac=round(f / t / PEAK_FP32, 4))
+        # the pair sweeps' HBM side: counter-measured bytes per launch over
+        # the launch's duration, and per interacting fluid pair
+        traffic = measured_traffic(k)
+        if traffic is not None:
+            kernels[k].update(hbm_gbps=round(traffic / t / 1e9, 1), hbm_frac=round(traffic / t / PEAK_HBM, 4),
+                              hbm_bytes_per_pair=round(traffic / (pc["ff"] + pc["fw"]), 2))
     dens_bytes = DENSITY_BYTES_PARTICLE * nf
     kernels["density"] = dict(ms=round(stage["density"], 4),
                               gbps=round(dens_bytes / (stage["density"] * 1e-3) / 1e9, 1),

@@ -150,6 +150,29 @@ __device__ __forceinline__ int stencil_row(int dy, int dz) {
     return D == 3 ? (dz + 1) * 3 + (dy + 1) : (dy + 1);
 }
 
+// Order in which every neighbour loop visits the stencil rows: each row
+// followed by its mirror image (dy, dz) -> (-dy, -dz), the centre row last
+// (3-D: 0, 8, 1, 7, 2, 6, 3, 5, 4).  A particle's pair counts in a row and
+// in its mirror vary in opposite directions with its place in the cell, so
+// a loop over the two together keeps the lanes of a wave evenly loaded.
+template <int D>
+constexpr int kRows = D == 3 ? 9 : 3;
+
+template <int D>
+__device__ __forceinline__ int row_at(int k) {
+    constexpr int last = kRows<D> - 1;
+    return k == last ? last / 2 : ((k & 1) ? last - (k >> 1) : (k >> 1));
+}
+
+// (y, z) of stencil row r around the cell row (cy, cz); false when outside
+// the grid.
+template <typename T, int D>
+__device__ __forceinline__ bool row_cell(const Par<T>& P, int r, int cy, int cz, int& y, int& z) {
+    y = cy + r % 3 - 1;
+    z = D == 3 ? cz + r / 3 - 1 : 0;
+    return y >= 0 && y < P.ny && z >= 0 && z < (D == 3 ? P.nz : 1);
+}
+
 // One stencil row as the walk, the mask builder and the mask sweep all see
 // it: cell starts and the (possibly trimmed) candidate range.
 struct Row {
@@ -189,19 +212,17 @@ __device__ __forceinline__ bool row_of(const Par<T>& P, const int32_t* __restric
     return true;
 }
 
-// Iterate the rows of query (c, oi); g(row, sy, sz) is called per row kept.
+// Iterate the rows of query (c, oi) in the order of row_at; g(row, sy, sz)
+// is called per row kept.
 template <typename T, int D, typename G>
 __device__ __forceinline__ void for_rows(const Par<T>& P, const int32_t* __restrict__ start,
                                          const int c[3], const T oi[3], G&& g) {
-    const int zlo = D == 3 ? max(c[2] - 1, 0) : 0;
-    const int zhi = D == 3 ? min(c[2] + 1, P.nz - 1) : 0;
-    const int ylo = max(c[1] - 1, 0), yhi = min(c[1] + 1, P.ny - 1);
-    for (int z = zlo; z <= zhi; ++z) {
-        for (int y = ylo; y <= yhi; ++y) {
-            Row R;
-            if (!row_of<T, D>(P, start, c, oi, y, z, R)) continue;
-            g(R, T(y - c[1]) * P.L, T(z - c[2]) * P.L);
-        }
+    for (int k = 0; k < kRows<D>; ++k) {
+        int y, z;
+        if (!row_cell<T, D>(P, row_at<D>(k), c[1], c[2], y, z)) continue;
+        Row R;
+        if (!row_of<T, D>(P, start, c, oi, y, z, R)) continue;
+        g(R, T(y - c[1]) * P.L, T(z - c[2]) * P.L);
     }
 }
 
@@ -504,68 +525,178 @@ __device__ __forceinline__ void mask_staged(const Par<T>& P, const int32_t* __re
                                             const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
                                             int64_t n, int64_t i, F&& f) {
     const int lane = threadIdx.x & 63;
-    const int zlo = D == 3 ? max(S.cz - 1, 0) : 0;
-    const int zhi = D == 3 ? min(S.cz + 1, P.nz - 1) : 0;
-    const int ylo = max(S.cy - 1, 0), yhi = min(S.cy + 1, P.ny - 1);
-    for (int z = zlo; z <= zhi; ++z) {
-        for (int y = ylo; y <= yhi; ++y) {
-            Row R;
-            const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
-            if (!__any(kept)) continue;
-            const int row = P.nx * (y + P.ny * z);
-            const int ulo = start[row + max(S.cx0 - 1, 0)];
-            const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
-            const bool staged = uhi - ulo <= CAP;  // the same for every lane
-            if (staged) {
-                for (int k = lane; k < uhi - ulo; k += 64) {
-                    lds_put(sp, k, ld4(pk, ulo + k));
-                    lds_put(sv, k, ld4(vk, ulo + k));
-                }
-                wave_sync();
+    for (int k = 0; k < kRows<D>; ++k) {
+        int y, z;
+        if (!row_cell<T, D>(P, row_at<D>(k), S.cy, S.cz, y, z)) continue;
+        Row R;
+        const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
+        if (!__any(kept)) continue;
+        const int row = P.nx * (y + P.ny * z);
+        const int ulo = start[row + max(S.cx0 - 1, 0)];
+        const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
+        const bool staged = uhi - ulo <= CAP;  // the same for every lane
+        if (staged) {
+            for (int t = lane; t < uhi - ulo; t += 64) {
+                lds_put(sp, t, ld4(pk, ulo + t));
+                lds_put(sv, t, ld4(vk, ulo + t));
             }
-            if (kept)
-                masked_row<T, D>(P, R, mask, n, i, oi, T(y - c[1]) * P.L, T(z - c[2]) * P.L, staged, sp, sv, ulo,
-                                 pk, vk, f);
-            if (staged) wave_sync();  // every lane is done with this row's records
+            wave_sync();
         }
+        if (kept)
+            masked_row<T, D>(P, R, mask, n, i, oi, T(y - c[1]) * P.L, T(z - c[2]) * P.L, staged, sp, sv, ulo, pk,
+                             vk, f);
+        if (staged) wave_sync();  // every lane is done with this row's records
+    }
+}
+
+// One stencil row of a block whose particles lie in one row of cells (S):
+// this thread's row (kept when it has candidates) and the block's index
+// range [ulo, ulo + n) of the row, which holds every thread's candidates.
+template <typename T>
+struct BlockRow {
+    Row R;
+    bool kept;
+    int ulo, n;
+    T sy, sz;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ BlockRow<T> block_row(const Par<T>& P, const int32_t* __restrict__ start,
+                                                 const WaveSpan& S, bool on, const int c[3], const T oi[3], int r) {
+    BlockRow<T> B;
+    B.kept = false;
+    B.ulo = 0;
+    B.n = 0;
+    // c[1], c[2] are the block's (S.cy, S.cz): the shifts of a row and of
+    // its mirror image are exact negatives of each other
+    B.sy = T(r % 3 - 1) * P.L;
+    B.sz = D == 3 ? T(r / 3 - 1) * P.L : T(0);
+    int y, z;
+    if (!row_cell<T, D>(P, r, S.cy, S.cz, y, z)) return B;  // outside the grid for the whole block
+    const int row = P.nx * (y + P.ny * z);
+    B.ulo = start[row + max(S.cx0 - 1, 0)];
+    B.n = start[row + min(S.cx1 + 1, P.nx - 1) + 1] - B.ulo;
+    B.kept = on && row_of<T, D>(P, start, c, oi, y, z, B.R);
+    return B;
+}
+
+// One row on its own: staged in LDS when it fits (CAP records), else
+// gathered from memory.  Every thread of the block calls it.
+template <typename T, int D, int CAP, typename F>
+__device__ __forceinline__ void block_single(const Par<T>& P, const BlockRow<T>& B, const Rec<T>* __restrict__ pk,
+                                             const Rec<T>* __restrict__ vk, SPH_LDS Rec<T>* sp,
+                                             SPH_LDS Rec<T>* sv, const T oi[3], const uint64_t* __restrict__ mask,
+                                             int64_t n, int64_t i, F&& f) {
+    if (!__syncthreads_or(B.kept)) return;
+    const bool staged = B.n <= CAP;  // the same for every thread
+    if (staged) {
+        for (int t = threadIdx.x; t < B.n; t += blockDim.x) {
+            lds_put(sp, t, ld4(pk, B.ulo + t));
+            lds_put(sv, t, ld4(vk, B.ulo + t));
+        }
+        __syncthreads();
+    }
+    if (B.kept) masked_row<T, D>(P, B.R, mask, n, i, oi, B.sy, B.sz, staged, sp, sv, B.ulo, pk, vk, f);
+    if (staged) __syncthreads();  // every thread is done with this row's records
+}
+
+// A row and its mirror image staged together (a at [0, a.n), b at
+// [a.n, a.n + b.n)) and swept in one loop: each lane takes its pairs of a,
+// then of b, in the order of two separate rows, so the sums are the same;
+// the loop runs to the busiest lane's total over both rows instead of to
+// the busiest lane of each.  A lane's state is the word it is on (bits, LDS
+// index lb of its bit 0), the second word of the same row (w1), the words of
+// b still to come, and the row's own-cell range and y/z shift.
+template <typename T, int D, typename F>
+__device__ __forceinline__ void block_pair(const Par<T>& P, const BlockRow<T>& a, const BlockRow<T>& b,
+                                           const SPH_LDS Rec<T>* sp, const SPH_LDS Rec<T>* sv, const T oi[3],
+                                           const uint64_t* __restrict__ mask, int64_t n, int64_t i, F&& f) {
+    uint64_t bits = 0, w1 = 0, b0 = 0, b1 = 0;
+    int lb = 0, ljm = 0, ljp = 0, off = 0;
+    uint32_t cyz = 0;
+    if (a.kept) {
+        bits = mask[(int64_t)(a.R.r * kMaskWords + 0) * n + i];
+        if (a.R.j1 - a.R.base > 64) w1 = mask[(int64_t)(a.R.r * kMaskWords + 1) * n + i];
+        lb = a.R.base - a.ulo;
+        ljm = a.R.jm - a.ulo;
+        ljp = a.R.jp - a.ulo;
+        off = a.ulo;
+        cyz = a.R.cyz;
+    }
+    if (b.kept) {
+        b0 = mask[(int64_t)(b.R.r * kMaskWords + 0) * n + i];
+        if (b.R.j1 - b.R.base > 64) b1 = mask[(int64_t)(b.R.r * kMaskWords + 1) * n + i];
+    }
+    T sy = a.sy, sz = a.sz;
+    bool in_a = true;
+    while (true) {
+        if (bits == 0) {
+            if (w1 != 0) {  // second word of the same row
+                bits = w1;
+                w1 = 0;
+                lb += 64;
+            } else if (in_a && b.kept) {  // on to the mirror row
+                in_a = false;
+                bits = b0;
+                w1 = b1;
+                lb = b.R.base - b.ulo + a.n;
+                ljm = b.R.jm - b.ulo + a.n;
+                ljp = b.R.jp - b.ulo + a.n;
+                off = b.ulo - a.n;
+                cyz = b.R.cyz;
+                sy = -sy;
+                sz = -sz;
+                if (bits == 0) {
+                    bits = w1;
+                    w1 = 0;
+                    lb += 64;
+                }
+            }
+            if (bits == 0) break;
+        }
+        const int t = lb + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int ix = t < ljm ? -1 : (t < ljp ? 0 : 1);
+        const Rec<T> q = lds_get(sp, t);
+        const Rec<T> u = lds_get(sv, t);
+        T d[3];
+        const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(t, ljm, ljp, P.L), sy, sz, d);
+        f(t + off, d, r2, cyz | ((uint32_t)(ix + 1) << kIdxBits), q, u);
     }
 }
 
 // Block-level form of mask_staged, for a block whose particles all lie in one
-// row of cells (S spans the block): the block stages each stencil row once
-// (up to CAP records) between block barriers, and every thread reads its
-// masked neighbours from there.  Every thread of the block must call it.
+// row of cells (S spans the block): the rows go in the order of row_at, a row
+// and its mirror image staged and swept together when both fit in CAP
+// records, else one at a time (each staged when it fits, else gathered).
+// Every thread of the block must call it.
 template <typename T, int D, int CAP, typename F>
 __device__ __forceinline__ void mask_block(const Par<T>& P, const int32_t* __restrict__ start,
                                            const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
                                            SPH_LDS Rec<T>* sp, SPH_LDS Rec<T>* sv, const WaveSpan& S, bool on,
                                            const int c[3], const T oi[3], const uint64_t* __restrict__ mask,
                                            int64_t n, int64_t i, F&& f) {
-    const int zlo = D == 3 ? max(S.cz - 1, 0) : 0;
-    const int zhi = D == 3 ? min(S.cz + 1, P.nz - 1) : 0;
-    const int ylo = max(S.cy - 1, 0), yhi = min(S.cy + 1, P.ny - 1);
-    for (int z = zlo; z <= zhi; ++z) {
-        for (int y = ylo; y <= yhi; ++y) {
-            Row R;
-            const bool kept = on && row_of<T, D>(P, start, c, oi, y, z, R);
-            if (!__syncthreads_or(kept)) continue;
-            const int row = P.nx * (y + P.ny * z);
-            const int ulo = start[row + max(S.cx0 - 1, 0)];
-            const int uhi = start[row + min(S.cx1 + 1, P.nx - 1) + 1];
-            const bool staged = uhi - ulo <= CAP;  // the same for every thread
-            if (staged) {
-                for (int k = threadIdx.x; k < uhi - ulo; k += blockDim.x) {
-                    lds_put(sp, k, ld4(pk, ulo + k));
-                    lds_put(sv, k, ld4(vk, ulo + k));
-                }
-                __syncthreads();
+    constexpr int NP = kRows<D> / 2;  // mirror pairs; the centre row comes after them
+    for (int g = 0; g < NP; ++g) {
+        const BlockRow<T> a = block_row<T, D>(P, start, S, on, c, oi, row_at<D>(2 * g));
+        const BlockRow<T> b = block_row<T, D>(P, start, S, on, c, oi, row_at<D>(2 * g + 1));
+        if (!__syncthreads_or(a.kept || b.kept)) continue;
+        if (a.n + b.n <= CAP) {  // the same for every thread
+            for (int t = threadIdx.x; t < a.n + b.n; t += blockDim.x) {
+                const int j = t < a.n ? a.ulo + t : b.ulo + (t - a.n);
+                lds_put(sp, t, ld4(pk, j));
+                lds_put(sv, t, ld4(vk, j));
             }
-            if (kept)
-                masked_row<T, D>(P, R, mask, n, i, oi, T(y - c[1]) * P.L, T(z - c[2]) * P.L, staged, sp, sv, ulo,
-                                 pk, vk, f);
-            if (staged) __syncthreads();  // every thread is done with this row's records
+            __syncthreads();
+            block_pair<T, D>(P, a, b, sp, sv, oi, mask, n, i, f);
+            __syncthreads();  // every thread is done with these records
+        } else {
+            block_single<T, D, CAP>(P, a, pk, vk, sp, sv, oi, mask, n, i, f);
+            block_single<T, D, CAP>(P, b, pk, vk, sp, sv, oi, mask, n, i, f);
         }
     }
+    const BlockRow<T> m = block_row<T, D>(P, start, S, on, c, oi, row_at<D>(kRows<D> - 1));
+    block_single<T, D, CAP>(P, m, pk, vk, sp, sv, oi, mask, n, i, f);
 }
 
 // Lanes of a wave sweep a row of the stencil together, so a wave runs as

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kBlock)
 // Records per wave staged in LDS for one stencil row (a row of a wave that
 // spans about four cells holds ~100 particles; longer rows are gathered).
 // A block staging for all its waves at once has kWaves * kStage records.
-constexpr int kStage = 160;
+constexpr int kStage = 192;
 constexpr int kWaves = kBlock / 64;
 
 // The fluid-fluid part of a pair sweep for particle i: block-staged when the
@@ -650,8 +650,14 @@ __global__ void __launch_bounds__(kBlock)
 //   dv_i/dt += m F/(rho_i rho_j) [-2 p* r_ij + 2 mu r^2/(r^2 + eta^2) v_ij].
 // ---------------------------------------------------------------------------
 
+// Waves per SIMD the FP32 momentum sweep is held to (80 VGPRs): one more
+// wave in flight than its register count would give hides more of the
+// neighbour loop's LDS latency than the few spilled registers cost.
+template <typename T>
+constexpr int kMomentumWaves = sizeof(T) == 4 ? 6 : 1;
+
 template <typename T, int D, bool MP>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     k_momentum(Par<T> P, NbrMask LF, NbrMask LW, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                const int32_t* __restrict__ pid, const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
