@@ -267,7 +267,7 @@ struct PackSrc {
 // contiguous index range; the cell of j inside the row follows from the
 // row's cell starts.  f(j, d, r2, code, q) receives d = r_i - r_j, the
 // shift code of the pair and j's record from the source.  Pairs come row
-// by row in ascending j.
+// by row, the rows in the order of row_at, each in ascending j.
 template <typename T, int D, typename S, typename F>
 __device__ __forceinline__ void walk_src(const Par<T>& P, const int32_t* __restrict__ start, const S& src,
                                          const int c[3], const T oi[3], F&& f) {

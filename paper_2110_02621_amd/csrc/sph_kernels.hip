@@ -342,8 +342,15 @@ __global__ void __launch_bounds__(kBlock)
 
 // Records per wave staged in LDS for one stencil row (a row of a wave that
 // spans about four cells holds ~100 particles; longer rows are gathered).
-// A block staging for all its waves at once has kWaves * kStage records.
-constexpr int kStage = 192;
+// A block staging for all its waves at once has kWaves * kStage records,
+// enough for a row and its mirror image of a block in one row of cells
+// (~2 x 290 on a full lattice).  The continuity sweep needs fewer registers
+// and stages fewer records (more pairs of rows go one row at a time), which
+// fits a seventh block per CU and is faster; the mask builder stages
+// position records only, and more of them.
+constexpr int kStage = 192;   // momentum: 2 x 768 records per block, 6 blocks (80 VGPRs)
+constexpr int kStageC = 160;  // continuity: 2 x 640 records per block, 7 blocks
+constexpr int kStageM = 256;  // mask builder: 256 position records per wave
 constexpr int kWaves = kBlock / 64;
 
 // The fluid-fluid part of a pair sweep for particle i: block-staged when the
@@ -352,7 +359,7 @@ constexpr int kWaves = kBlock / 64;
 // whose masks overflowed walk the cells.  fluid(j, d, r2, code, q, u) takes
 // the position record q and velocity record u of j; fluid_g(j, d, r2, code,
 // q) the same with u loaded from memory.
-template <typename T, int D, typename F, typename G>
+template <int STAGE, typename T, int D, typename F, typename G>
 __device__ __forceinline__ void fluid_sweep(const Par<T>& P, const NbrMask& LF, const int32_t* __restrict__ fstart,
                                             const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk,
                                             const int32_t* __restrict__ key, Rec<T>* stage, bool block_mode,
@@ -360,8 +367,8 @@ __device__ __forceinline__ void fluid_sweep(const Par<T>& P, const NbrMask& LF, 
                                             const int c[3], const T oi[3], F&& fluid, G&& fluid_g) {
     if (block_mode) {
         const bool m = act && LF.count[i] >= 0;
-        mask_block<T, D, kWaves * kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage,
-                                          (SPH_LDS Rec<T>*)(stage + kWaves * kStage), SB, m, c, oi, LF.mask,
+        mask_block<T, D, kWaves * STAGE>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)stage,
+                                         (SPH_LDS Rec<T>*)(stage + kWaves * STAGE), SB, m, c, oi, LF.mask,
                                           LF.n, i, fluid);
         if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
         return;
@@ -370,8 +377,8 @@ __device__ __forceinline__ void fluid_sweep(const Par<T>& P, const NbrMask& LF, 
     if (LF.mask && S.one_row) {
         const bool m = act && LF.count[i] >= 0;
         const int wv = threadIdx.x >> 6;
-        mask_staged<T, D, kStage>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)(stage + wv * kStage),
-                                  (SPH_LDS Rec<T>*)(stage + (kWaves + wv) * kStage), S, m, c, oi, LF.mask,
+        mask_staged<T, D, STAGE>(P, fstart, pk, vk, (SPH_LDS Rec<T>*)(stage + wv * STAGE),
+                                 (SPH_LDS Rec<T>*)(stage + (kWaves + wv) * STAGE), S, m, c, oi, LF.mask,
                                   LF.n, i, fluid);
         if (act && !m) walk_src<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, fluid_g);
     } else if (act) {
@@ -573,7 +580,7 @@ __global__ void __launch_bounds__(kBlock)
                  const int32_t* __restrict__ pid, const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
                  const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                  const Rec<T>* __restrict__ wk, T* __restrict__ drho_out, Rec<T>* __restrict__ pk_out) {
-    __shared__ Rec<T> stage[2 * kWaves * kStage];
+    __shared__ Rec<T> stage[2 * kWaves * kStageC];
     __shared__ int perm[kBlock];
     __shared__ int hist[16];
     const int64_t blk0 = (int64_t)logical_block() * kBlock;
@@ -618,7 +625,8 @@ __global__ void __launch_bounds__(kBlock)
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
     };
-    fluid_sweep<T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid, fluid_g);
+    fluid_sweep<kStageC, T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid,
+                               fluid_g);
     if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
@@ -727,7 +735,8 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
     };
-    fluid_sweep<T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid, fluid_g);
+    fluid_sweep<kStage, T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid,
+                              fluid_g);
     if (!act) return;
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
@@ -792,7 +801,7 @@ __global__ void __launch_bounds__(kBlock)
                   const Rec<T>* __restrict__ wk, const int32_t* __restrict__ wstart,
                   uint64_t* __restrict__ mf, int32_t* __restrict__ cf, uint64_t* __restrict__ mw,
                   int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
-    __shared__ Rec<T> stage_p[kBlock / 64][kStage];
+    __shared__ Rec<T> stage_p[kBlock / 64][kStageM];
     const int64_t i0 = global_index();
     const int64_t ib = i0 - (threadIdx.x & 63);
     if (ib >= nf) return;  // the whole wave is past the end
@@ -805,7 +814,7 @@ __global__ void __launch_bounds__(kBlock)
     const WaveSpan S = wave_span(P, key, ib, nf);
     int n = 0;
     if (S.one_row)
-        n = build_mask_staged<T, D, kStage>(P, fstart, pk, (SPH_LDS Rec<T>*)stage_p[threadIdx.x >> 6], S, act,
+        n = build_mask_staged<T, D, kStageM>(P, fstart, pk, (SPH_LDS Rec<T>*)stage_p[threadIdx.x >> 6], S, act,
                                             c, oi, mf, nf, i);
     else if (act)
         n = build_mask<T, D>(P, fstart, PackSrc<T>{pk}, c, oi, mf, nf, i);
