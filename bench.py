@@ -46,6 +46,18 @@ FLOPS_PAIR = {
 SORT_BYTES_PARTICLE = 116
 SORT_BYTES_CELL = 24
 DENSITY_BYTES_PARTICLE = 88
+# Compulsory HBM bytes (lower bounds, FP32, 3-D, every record read once)
+# per fluid particle of the mask builder (reads offset record, key: 20;
+# writes nine row words, two counts: 80), the continuity sweep (reads both
+# records, key, count, nine row words: 112; writes the density and its
+# record: 20) and the momentum sweep (the same reads: 112; writes dv/dt,
+# velocity, its record, sigma: 44), and per wall particle of the wall
+# pressure (key, record, count; writes p_w and the record: 44).  Second
+# mask words and the fluid-wall rows are left out.
+MASKS_BYTES_PARTICLE = 100
+CONTINUITY_BYTES_PARTICLE = 132
+MOMENTUM_BYTES_PARTICLE = 156
+WALL_BC_BYTES_WALL = 44
 
 # HBM bytes per launch of the two pair sweeps on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000,
@@ -128,6 +140,25 @@ def measured_traffic(kernel):
     if h.hexdigest() != TRAFFIC["sources_sha256"]:
         return None
     return TRAFFIC.get(kernel)
+
+
+def copy_rate(torch, gib=2.0, reps=10):
+    """Bytes read plus written per second of a plain device-to-device copy
+    of `gib` GiB (the HBM rate a streaming kernel reaches in practice)."""
+    a = torch.ones(int(gib * 2 ** 30) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return rate
 
 
 def pair_counts(S):
@@ -213,6 +244,21 @@ def main():
     sort_bytes = SORT_BYTES_PARTICLE * nf + SORT_BYTES_CELL * int(S.desc.n_cells)
     kernels["cells"] = dict(ms=round(stage["sort"], 4),
                             sort_gbps_lower_bound=round(sort_bytes / (stage["sort"] * 1e-3) / 1e9, 1))
+    # compulsory bytes per stage and per step against the published peak and
+    # the measured copy rate
+    alg = {"density": dens_bytes, "sort": sort_bytes + MASKS_BYTES_PARTICLE * nf,
+           "wall_bc": WALL_BC_BYTES_WALL * nw, "continuity": CONTINUITY_BYTES_PARTICLE * nf,
+           "momentum": MOMENTUM_BYTES_PARTICLE * nf}
+    copy_bw = copy_rate(torch)
+    step_hbm = dict(compulsory_bytes=sum(alg.values()), copy_gbps=round(copy_bw / 1e9, 1))
+    t_stages = sum(stage.values()) * 1e-3
+    step_hbm.update(gbps=round(step_hbm["compulsory_bytes"] / t_stages / 1e9, 1),
+                    hbm_frac=round(step_hbm["compulsory_bytes"] / t_stages / PEAK_HBM, 4),
+                    copy_frac=round(step_hbm["compulsory_bytes"] / t_stages / copy_bw, 4),
+                    by_stage={k: dict(bytes=v, gbps=round(v / (stage[k] * 1e-3) / 1e9, 1),
+                                      hbm_frac=round(v / (stage[k] * 1e-3) / PEAK_HBM, 4),
+                                      copy_frac=round(v / (stage[k] * 1e-3) / copy_bw, 4))
+                              for k, v in alg.items()})
     dom = max(("continuity", "momentum"), key=lambda k: stage[k])
     ach = flops[dom] / (stage[dom] * 1e-3)
     roofline = dict(bound="alu", achieved=round(ach / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
@@ -364,6 +410,7 @@ def main():
         "adjoint": adj,
         "roofline": roofline,
         "roofline_frac_unpacked_fp32": round(ach / PEAK_FP32_UNPACKED, 4),
+        "step_hbm": step_hbm,
         "kernels": kernels,
         "pairs": pc,
         "status": st,
