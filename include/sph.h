@@ -306,8 +306,10 @@ int sph_neighbours(const sph_desc *desc, const sph_buffers *buf, int which, cons
 /* frames (recomputed bit for bit, not differentiated); branches (the    */
 /* limiter, max() of Eq. (17), delta < 1) take the forward's side, with  */
 /* derivative 0 at max(x, 0)'s kink.  The adjoint runs in FP64.          */
-/* It covers the single-phase step in a fixed tank: every backward call */
-/* returns SPH_ERR_CONFIG when desc->two_phase or desc->motion_freq is   */
+/* It covers the single-phase step, in a fixed or a moving tank (the     */
+/* prescribed motion does not depend on theta: its velocity kicks pass   */
+/* through, and Eq. (12) takes g - a_w - X'' at each frame's own time);  */
+/* every backward call returns SPH_ERR_CONFIG when desc->two_phase is    */
 /* set.                                                                  */
 /* ------------------------------------------------------------------ */
 
@@ -333,6 +335,9 @@ typedef struct sph_frame {
      * when all are given the backward sweeps visit them instead of walking */
     const uint64_t *nbr_ff, *nbr_fw, *nbr_wf;
     const int32_t *cnt_ff, *cnt_fw, *cnt_wf;
+    /* step count of this state (time nstep * dt): set by sph_step_frame
+     * for the state it records; the caller sets it for frame 0 */
+    int64_t nstep;
 } sph_frame;
 
 /* Adjoint state (device, FP64, particle-id order) and workspace. */
@@ -353,7 +358,7 @@ size_t sph_adjoint_work_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_w
  * the current sorted order) and the state at r^{n+1} into the arrays of
  * next (written through its pointers, which must be distinct device
  * buffers of the sizes stated in sph_frame; the mask fields are copied only
- * when buf has masks and next provides them). */
+ * when buf has masks and next provides them), and next->nstep. */
 int sph_step_frame(const sph_desc *desc, sph_buffers *buf, void *sigma_cur, sph_frame *next,
                    void *stream);
 

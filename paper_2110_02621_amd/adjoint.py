@@ -28,7 +28,8 @@ class Frame(C.Structure):
                 ("rho", C.c_void_p), ("sigma", C.c_void_p), ("vh", C.c_void_p), ("rt", C.c_void_p),
                 ("pw", C.c_void_p),
                 ("nbr_ff", C.c_void_p), ("nbr_fw", C.c_void_p), ("nbr_wf", C.c_void_p),
-                ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p)]
+                ("cnt_ff", C.c_void_p), ("cnt_fw", C.c_void_p), ("cnt_wf", C.c_void_p),
+                ("nstep", C.c_int64)]
 
 
 class Adjoint(C.Structure):
@@ -109,6 +110,9 @@ class FramePool:
     def struct(f):
         fr = Frame()
         for name, _ in Frame._fields_:
+            if name == "nstep":
+                fr.nstep = int(f.get("nstep", 0))
+                continue
             v = f.get(name)
             setattr(fr, name, (_p(v).value or None) if v is not None else None)
         return fr
@@ -124,6 +128,7 @@ def recompute_segment(S, pool, start_state, nsteps, first_frame_extra=None):
         f0[k] = start_state[k]
     f0.pop("vh", None)
     f0.pop("pw", None)
+    f0["nstep"] = start_state["nstep"]
     if first_frame_extra:
         f0.update(first_frame_extra)
     stream = S._stream()
@@ -131,6 +136,7 @@ def recompute_segment(S, pool, start_state, nsteps, first_frame_extra=None):
         nxt = FramePool.struct(pool.frames[n + 1])
         check(L.sph_step_frame(C.byref(S.desc), C.byref(S.buf), _p(pool.frames[n]["sigma"]),
                                C.byref(nxt), stream), "sph_step_frame")
+        pool.frames[n + 1]["nstep"] = nxt.nstep
     return [FramePool.struct(f) for f in pool.frames[:nsteps + 1]]
 
 

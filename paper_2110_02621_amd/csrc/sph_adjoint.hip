@@ -47,7 +47,9 @@ struct AdjPar {
     int penalty;
 };
 
-AdjPar make_adj(const sph_desc* d) {
+// Run constants at step `step` (the time of the state being reversed): in
+// a moving tank Eq. (12) takes g - a_w - X''(t) there.
+AdjPar make_adj(const sph_desc* d, int64_t step = 0) {
     AdjPar Q;
     const double h = d->h;
     Q.h = h;
@@ -64,9 +66,10 @@ AdjPar make_adj(const sph_desc* d) {
     Q.dt = d->dt;
     Q.half_dt = 0.5 * d->dt;
     Q.sigma0 = d->sigma0;
+    const Motion mo = motion_at(d, step);
     for (int k = 0; k < 3; ++k) {
         Q.g[k] = d->g[k];
-        Q.gw[k] = d->g[k] - d->a_wall[k];
+        Q.gw[k] = d->g[k] - d->a_wall[k] - mo.A[k];
     }
     Q.penalty = d->penalty_all ? 1 : 0;
     return Q;
@@ -631,8 +634,7 @@ AdjWork adj_layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
 }
 
 int check_adj(const sph_desc* d, const sph_buffers* b, const sph_adjoint* a) {
-    if (d->two_phase || d->motion_freq != 0.0)
-        return SPH_ERR_CONFIG;  // the backward covers the single-phase step in a fixed tank
+    if (d->two_phase) return SPH_ERR_CONFIG;  // the backward covers the single-phase step
     if (!a || !a->theta || !a->work) return SPH_ERR_ARG;
     if (a->work_bytes < sph_adjoint_work_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
     if (((uintptr_t)a->work & 255) != 0) return SPH_ERR_ARG;
@@ -693,7 +695,7 @@ int wall_bc_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, s
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nw == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    const AdjPar Q = make_adj(d);
+    const AdjPar Q = make_adj(d, f->nstep);
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     hipLaunchKernelGGL((k_wall_bwd<T, D>), dim3(grid_for(nw)), dim3(kBlock), 0, st, P, Q,
                        fmask(f->nbr_wf, f->cnt_wf, nw), nf, nw,
@@ -738,7 +740,7 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
     const int64_t nf = b->n_fluid, nw = b->n_wall;
     if (nf == 0) return SPH_OK;
     const Par<T> P = make_par<T>(d);
-    const AdjPar Q = make_adj(d);
+    const AdjPar Q = make_adj(d, f->nstep);
     const AdjWork w = adj_layout(d, nf, nw, a->work);
     const int nb = grid_for(nf);
     // a^0 = MOM(r^0, v^0, rho^0, p_w^0): Abar = ab (no kick), rho adjoint in place

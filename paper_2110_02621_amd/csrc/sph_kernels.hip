@@ -1320,6 +1320,7 @@ int step_frame_t(const sph_desc* d, sph_buffers* b, void* sigma_cur, sph_frame* 
     }
     hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, st, b->diag);
     SPH_LAUNCH_CHECK();
+    nx->nstep = b->nstep;
     return SPH_OK;
 }
 

@@ -17,6 +17,7 @@ particles on the floor and the side walls and an open top (Fig. 1).
 from __future__ import annotations
 
 import math
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -395,6 +396,18 @@ def sloshing_tank(dim=3, dx=0.01, two_phase=True, amp=SLOSH_A0, freq=SLOSH_F0, l
                  penalty_all=not two_phase, meta=dict(tank=SLOSH_TANK[:dim - 1] + (D,),
                                                       layers=layers),
                  motion_amp=tuple(amp_v), motion_freq=float(freq), **extra)
+
+
+def shaken(sc, amp=0.05, freq=5.0, axis=0):
+    """``sc`` in a tank translated along ``axis`` by X(t) = amp sin(2 pi
+    freq t) (walls, probe and all), the fluid at rest relative to the tank
+    at t = 0 (moving with X'(0))."""
+    a = [0.0, 0.0, 0.0]
+    a[axis] = float(amp)
+    fv = np.array(sc.fluid_v, dtype=np.float64, copy=True)
+    fv[:, axis] += amp * 2.0 * math.pi * freq
+    return dataclasses.replace(sc, name=sc.name + "_shaken", fluid_v=fv, motion_amp=tuple(a),
+                               motion_freq=float(freq))
 
 
 WEDGE_H = 5.5  # wedge height h_w (Sec. 4.5)

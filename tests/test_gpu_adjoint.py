@@ -10,6 +10,10 @@ theta = (mu, gamma_p, c0, H); J = sum_n dt mean(p_w over the probe).
     on mu through that term only, so its curvature in mu is of the order of
     the square of that share and the step adds no visible truncation).
 Checkpointing (K < steps) must not change the result.
+The same checks hold in a shaken tank (the dam break translated along x by
+0.05 sin(2 pi 5 t) m, |X''| up to 49 m/s^2): the motion does not depend on
+theta, but Eq. (12) takes g - X''(t) at every step, so the backward has to
+follow the forward's time.
 """
 import numpy as np
 import pytest
@@ -40,6 +44,8 @@ def make(base, theta, **kw):
     mu, gp, c0, H = theta
     if base == "dam":
         return scenes.dam_break_2d(mu=mu, gamma_p=gp, c0=c0, column_height=H, **kw)
+    if base == "dam_shaken":
+        return scenes.shaken(scenes.dam_break_2d(mu=mu, gamma_p=gp, c0=c0, column_height=H, **kw))
     if base == "jet":
         return scenes.wall_jet_2d(mu=mu, gamma_p=gp, c0=c0, **kw)
     raise ValueError(base)
@@ -116,6 +122,56 @@ def test_adjoint_fp64_matches_gpu_finite_differences(adj):
     r2 = adj.probe_gradient(sc, precision="f64", K=steps)
     assert np.allclose([r2["grad"][n] for n in NAMES], g, rtol=1e-12, atol=0)
     assert r2["J"] == r["J"]
+
+
+def test_adjoint_shaken_tank_fp64_matches_gpu_finite_differences(adj):
+    th = theta0(scenes.dam_break_2d(dx=0.04))
+    steps = 40
+    sc = make("dam_shaken", th, dx=0.04, steps=steps)
+    print(f"[adj64-shaken] nf={sc.n_fluid} nw={sc.n_wall} f0={sc.motion_freq}", flush=True)
+    r = adj.probe_gradient(sc, precision="f64", K=15)
+    g = np.array([r["grad"][n] for n in NAMES])
+    fd = fd_gpu(adj, "dam_shaken", th, steps, "f64", kw=dict(dx=0.04))
+    compare(g, fd, th, 1e-5, "shaken dam f64")
+    r2 = adj.probe_gradient(sc, precision="f64", K=steps)
+    assert np.allclose([r2["grad"][n] for n in NAMES], g, rtol=1e-12, atol=0)
+    assert r2["J"] == r["J"]
+
+
+def test_adjoint_shaken_tank_fp32_matches_oracle_finite_differences(adj):
+    kw = dict(dx=0.02)
+    th = theta0(scenes.dam_break_2d(**kw))
+    steps = 100
+    sc = make("dam_shaken", th, steps=steps, **kw)
+    print(f"[adj32-shaken] nf={sc.n_fluid} nw={sc.n_wall} f0={sc.motion_freq}", flush=True)
+    r = adj.probe_gradient(sc, precision="f32", K=25)
+    g = np.array([r["grad"][n] for n in NAMES])
+    # dJ/dmu is 4x smaller here than in the fixed tank while its errors are
+    # absolute: the oracle differences carry FP64 rounding of J (~3e-9 on
+    # dJ/dmu in both tanks with a 1e-1 step), so mu takes a 0.5 step (J is
+    # linear in mu far below that rounding), and the FP32 forward's error of
+    # the viscous term (~1e-6 on dJ/dmu in both tanks) takes a 1e-2 bar.
+    fd = fd_oracle("dam_shaken", th, steps, rel=(0.5,) + STEP[1:], kw=kw)
+    P = O.params_from_scene(sc)
+    st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe).step(steps)
+    print(f"  J gpu {r['J']:.9e} oracle {st.J:.9e}", flush=True)
+    assert abs(r["J"] - st.J) <= 1e-4 * abs(st.J)
+    compare(g, fd, th, (1e-2, 1e-3, 1e-3, 1e-3), "shaken dam f32 vs oracle")
+    r64 = adj.probe_gradient(sc, precision="f64", K=25)
+    g64 = np.array([r64["grad"][n] for n in NAMES])
+    compare(g64, fd, th, 2e-5, "shaken dam f64 vs oracle")
+
+
+def test_shaking_moves_the_gradient(adj):
+    # the shaken case is not the fixed tank in disguise: its c0 and H
+    # components differ from the fixed tank's by far more than the bars above
+    th = theta0(scenes.dam_break_2d(dx=0.04))
+    still = adj.probe_gradient(make("dam", th, dx=0.04, steps=40), precision="f64", K=20)
+    shaken = adj.probe_gradient(make("dam_shaken", th, dx=0.04, steps=40), precision="f64", K=20)
+    for n in ("c0", "H"):
+        a, b = still["grad"][n], shaken["grad"][n]
+        print(f"  d J/d{n}: fixed {a:.6e} shaken {b:.6e}", flush=True)
+        assert abs(a - b) > 1e-2 * abs(b), n
 
 
 def test_adjoint_penalty_scene_fp64(adj):
