@@ -66,7 +66,7 @@ WALL_BC_BYTES_WALL = 44
 # kernel sources whose SHA-256 is recorded; once those change the traffic is
 # reported as null until the counters are taken again.
 TRAFFIC = {
-    "sources_sha256": "943dc1eb13137884a4b7602fbcae5f0688e216178afb70d05cc39695952c70df",
+    "sources_sha256": "4db7e0e1e562b4acea5075ec4b11656695c651e90d41c01a383ffb29f8856c64",
     "momentum": 2071.9e6 + 269.0e6,
     "continuity": 2087.0e6 + 139.7e6,
 }

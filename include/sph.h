@@ -127,6 +127,8 @@ typedef struct sph_desc {
  * two copies [0] and [1]; sel_vel / sel_rho name the copy that holds the
  * current v and rho - rho0 and are updated by the calls that swap them. */
 typedef struct sph_buffers {
+    /* at most 2^28 - 1 each in FP32, 2^27 - 1 in FP64 (every record array
+       stays below 4 GiB); larger counts get SPH_ERR_ARG */
     int64_t n_fluid;
     int64_t n_wall;
     /* fluid, length n_fluid unless stated */
@@ -202,7 +204,7 @@ int sph_configure(sph_desc *desc);
  * equal to the state it leaves; a caller that overwrites state arrays
  * itself must call sph_build_cells (or sph_init) before the next
  * sph_wall_bc or sph_forces. */
-size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
+size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);  /* 0 beyond the counts above */
 
 /* Loads the initial state and prepares the run (Sec. 3: the data is copied
  * to the device once, at the start).
@@ -351,7 +353,7 @@ typedef struct sph_adjoint {
     size_t work_bytes;
 } sph_adjoint;
 
-size_t sph_adjoint_work_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
+size_t sph_adjoint_work_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);  /* 0 beyond the limits */
 
 /* One forward step (exactly sph_step with nsteps = 1) that also records
  * the frames the backward needs: sigma at r^n into sigma_cur (T[n_fluid],

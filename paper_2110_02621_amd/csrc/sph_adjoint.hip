@@ -797,7 +797,7 @@ int init_bwd_t(const sph_desc* d, const sph_buffers* b, const sph_frame* f, doub
 extern "C" {
 
 size_t sph_adjoint_work_bytes(const sph_desc* d, int64_t n_fluid, int64_t n_wall) {
-    if (!d || n_fluid < 0 || n_wall < 0) return 0;
+    if (!d || n_fluid < 0 || n_wall < 0 || n_fluid > max_particles(d) || n_wall > max_particles(d)) return 0;
     return adj_layout(d, n_fluid, n_wall, nullptr).bytes;
 }
 

@@ -81,8 +81,9 @@ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
 // Element j of a device array through a 32-bit byte offset from the array's
 // (wave-uniform) base, so the load takes the scalar-base addressing form and
-// needs no 64-bit address arithmetic per lane.  Every array here has fewer
-// than 2^26 elements.
+// needs no 64-bit address arithmetic per lane.  The entry points refuse
+// particle counts whose record arrays would reach 4 GiB (2^28 particles in
+// FP32, 2^27 in FP64), so the offset never wraps.
 template <typename T>
 __device__ __forceinline__ T ldg(const T* __restrict__ p, int j) {
     return *(const T*)((const char*)p + (uint32_t)j * (uint32_t)sizeof(T));

@@ -197,10 +197,17 @@ inline int check_desc(const sph_desc* d) {
     return SPH_OK;
 }
 
+// Largest particle count of either set.  Every gather forms a 32-bit byte
+// offset from its array's base (ldg, ld4), so a record array stays below
+// 4 GiB: 2^28 - 1 particles in FP32 (16-byte records), 2^27 - 1 in FP64.
+inline int64_t max_particles(const sph_desc* d) {
+    return d->precision == SPH_F32 ? (int64_t{1} << 28) - 1 : (int64_t{1} << 27) - 1;
+}
+
 inline int check_buf(const sph_desc* d, const sph_buffers* b) {
     if (!b) return SPH_ERR_ARG;
     if (b->n_fluid < 0 || b->n_wall < 0) return SPH_ERR_ARG;
-    if (b->n_fluid > INT32_MAX - 1 || b->n_wall > INT32_MAX - 1) return SPH_ERR_ARG;
+    if (b->n_fluid > max_particles(d) || b->n_wall > max_particles(d)) return SPH_ERR_ARG;
     if (b->sel_vel < 0 || b->sel_vel > 1 || b->sel_rho < 0 || b->sel_rho > 1) return SPH_ERR_ARG;
     if (!b->scratch || b->scratch_bytes < sph_scratch_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
     if (((uintptr_t)b->scratch & 255) != 0) return SPH_ERR_ARG;

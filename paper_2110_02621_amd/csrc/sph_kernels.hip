@@ -1462,7 +1462,7 @@ int sph_configure(sph_desc* d) {
 }
 
 size_t sph_scratch_bytes(const sph_desc* d, int64_t n_fluid, int64_t n_wall) {
-    if (!d || n_fluid < 0 || n_wall < 0) return 0;
+    if (!d || n_fluid < 0 || n_wall < 0 || n_fluid > max_particles(d) || n_wall > max_particles(d)) return 0;
     return layout(d, n_fluid, n_wall, nullptr).bytes;
 }
 

@@ -86,3 +86,23 @@ def test_ctypes_structs_match_header_layout(cname, pyname, tmp_path):
     size, offs = _c_layout(cname, fields, tmp_path)
     assert ctypes.sizeof(cls) == size
     assert [getattr(cls, f).offset for f in fields] == offs
+
+
+def test_particle_count_limits():
+    # gathers use 32-bit byte offsets: record arrays must stay below 4 GiB,
+    # 2^28 - 1 particles per set in FP32 (16-byte records), 2^27 - 1 in FP64
+    from paper_2110_02621_amd import abi, scenes
+    from paper_2110_02621_amd.solver import make_desc
+    lib = ctypes.CDLL(LIB)
+    lib.sph_scratch_bytes.argtypes = [ctypes.POINTER(abi.Desc), ctypes.c_int64, ctypes.c_int64]
+    lib.sph_scratch_bytes.restype = ctypes.c_size_t
+    lib.sph_adjoint_work_bytes.argtypes = lib.sph_scratch_bytes.argtypes
+    lib.sph_adjoint_work_bytes.restype = ctypes.c_size_t
+    sc = scenes.dam_break_3d(dx=0.02)
+    for prec, top in (("f32", 2 ** 28 - 1), ("f64", 2 ** 27 - 1)):
+        d = make_desc(sc, prec)
+        for fn in (lib.sph_scratch_bytes, lib.sph_adjoint_work_bytes):
+            assert fn(ctypes.byref(d), top, 1000) > 0, prec
+            assert fn(ctypes.byref(d), 1000, top) > 0, prec
+            assert fn(ctypes.byref(d), top + 1, 1000) == 0, prec
+            assert fn(ctypes.byref(d), 1000, top + 1) == 0, prec
