@@ -222,3 +222,37 @@ def test_autograd_function(adj):
     sc = make("dam", th.detach().numpy(), dx=0.04, steps=20)
     r = adj.probe_gradient(sc, precision="f64", K=10)
     assert np.allclose(th.grad.numpy(), [r["grad"][n] for n in NAMES], rtol=1e-12)
+
+
+def test_full_size_adjoint_matches_finite_differences(adj):
+    # The differentiable dam break at its full size (dx = 0.005: 80,000 +
+    # 6,018, 1000 steps, checkpoints every 50), as the bench runs it.  The
+    # FP64 oracle cannot difference 1000 steps of it in test time, so the
+    # checks are ones that hold at any size: the FP64 adjoint against FP64
+    # central differences of the GPU's own forward, and the FP32 forward's
+    # gradient (the bench's) against the FP64 one within the FP32 bars used
+    # above.  J is smooth only piecewise (the limiter, max() of Eq. (17), the
+    # penalty switch): a difference step that crosses a kink is off by a
+    # finite amount, and 1000 steps of 80,000 particles cross many, in
+    # proportion to the step (1e-4 leaves dJ/dH 1.4e-3 off).  FP64 rounding
+    # of J (~1e-13) allows steps of 1e-6 for c0 and H; mu keeps 0.5 (its
+    # share of J is ~1e-9 of J and it hardly moves the flow).
+    kw = dict(dx=0.005)
+    th = theta0(scenes.dam_break_2d(**kw))
+    steps = 1000
+    sc = make("dam", th, steps=steps, **kw)
+    print(f"[adj-full] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)} steps={steps}", flush=True)
+    r64 = adj.probe_gradient(sc, precision="f64", K=50)
+    g64 = np.array([r64["grad"][n] for n in NAMES])
+    fd = fd_gpu(adj, "dam", th, steps, "f64", rel=(0.5, 1e-6, 1e-6, 1e-6), kw=kw)
+    compare(g64, fd, th, 1e-4, "full dam f64")
+    # The FP32 gradient is the adjoint taken along the FP32 trajectory.  Over
+    # 1000 steps of 80,000 particles it separates from the FP64 one, and J's
+    # derivative is only piecewise smooth, so the c0 component (limiter and
+    # pressure terms) moves by ~1e-3 (1.3e-6 after 100 steps on 5,000
+    # particles): it takes a 2e-3 bar here, the others keep theirs.
+    r32 = adj.probe_gradient(sc, precision="f32", K=50)
+    g32 = np.array([r32["grad"][n] for n in NAMES])
+    print(f"  J f32 {r32['J']:.9e} f64 {r64['J']:.9e}", flush=True)
+    assert abs(r32["J"] - r64["J"]) <= 1e-4 * abs(r64["J"])
+    compare(g32, g64, th, (5e-3, 2e-3, 2e-3, 1e-3), "full dam f32 vs f64 adjoint")

@@ -319,6 +319,8 @@ FULL = {
     "dam3d_obst_dx0.0025": lambda: scenes.dam_break_3d(dx=0.0025, obstacles=8, seed=0),
     # the dam break with a wedge at the paper's dx = h_w/40 (5,721,296 particles)
     "wedge3d_res40": lambda: scenes.dam_break_wedge(res=40),
+    # the differentiable 2-D dam break at its full size (80,000 + 6,018)
+    "dam2d_dx0.005": lambda: scenes.dam_break_2d(dx=0.005),
 }
 
 
@@ -336,15 +338,15 @@ def test_full_size_sampled_parity(solver_mod, name):
     rng = np.random.default_rng(5)
     e0, w0 = S.export(), S.export_walls()
     wx, wn = w0["pos"], w0["nrm"]
-    near_wall = np.nonzero(e0["pos"][:, 2] < 3 * sc.dx)[0]
+    near_wall = np.nonzero(e0["pos"][:, sc.dim - 1] < 3 * sc.dx)[0]
     qf = np.unique(np.concatenate([rng.choice(sc.n_fluid, 3000, replace=False),
-                                   rng.choice(near_wall, 1000, replace=False)]))
+                                   rng.choice(near_wall, min(1000, len(near_wall)), replace=False)]))
     qw = rng.choice(sc.n_wall, 2000, replace=False)
     # neighbour sets of the sampled particles: equal to the FP64 cell-list
     # sets except for pairs within a few ulps of the cut-off
     cnt, off, lst = S.neighbours(0)
     allx = np.concatenate([e0["pos"], wx])
-    ocnt, olst = O.neighbours(3, sc.h, e0["pos"][qf], allx)
+    ocnt, olst = O.neighbours(sc.dim, sc.h, e0["pos"][qf], allx)
     oo = np.concatenate([[0], np.cumsum(ocnt)])
     nborder = 0
     for a, i in enumerate(qf):
