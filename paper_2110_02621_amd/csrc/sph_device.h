@@ -816,4 +816,35 @@ __device__ __forceinline__ T wendland_F(const Par<T>& P, T r) {
     return P.gfac * (t * t * t);
 }
 
+// Distance of a pair in the neighbour sums: r^2 times its reciprocal square
+// root, with the reciprocal root of 1 at r = 0 so that the self pair gives
+// r = 0 exactly (one reciprocal root, no square root).  Every sum of W over
+// neighbours takes this form, so the number density a sweep hands over is
+// bit for bit the one the density update would sum.
+template <typename T>
+__device__ __forceinline__ T pair_r(T r2, T& rinv) {
+    rinv = rsq(r2 > T(0) ? r2 : T(1));
+    return r2 * rinv;
+}
+
+template <typename T>
+__device__ __forceinline__ T pair_r(T r2) {
+    T rinv;
+    return pair_r(r2, rinv);
+}
+
+// W(r) and W'(r)/r from one t = 1 - q/2 (W exactly as wendland_W gives it).
+template <typename T>
+struct KernelWF {
+    T W, F;
+};
+
+template <typename T>
+__device__ __forceinline__ KernelWF<T> wendland_WF(const Par<T>& P, T r) {
+    const T q = r * P.hinv;
+    const T t = T(1) - T(0.5) * q;
+    const T t2 = t * t;
+    return KernelWF<T>{P.alpha * (t2 * t2) * (T(1) + T(2) * q), P.gfac * (t2 * t)};
+}
+
 }  // namespace sph

@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(kBlock)
     if (sigma_in) {
         s = sigma_in[i];  // summed by the momentum sweep over the same pairs, in the same order
     } else {
-        auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, root(r2))); };
+        auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, pair_r(r2))); };
         visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, addW);
         if (nw > 0) visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
     }
@@ -605,12 +605,14 @@ __global__ void __launch_bounds__(kBlock)
     T sum = T(0);
     T sig = T(0), comp = T(0);  // two phases: sigma at these positions for the light phase
     auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
-        if (MP) kahan_add(sig, comp, wendland_W(P, root(r2)));
         // no branch for r = 0 (the particle itself, or a coincident one):
         // every part of its term carries r or d, so it adds an exact zero,
-        // and the velocity record is read without waiting on r2
-        const T r = root(r2);
-        const T F = wendland_F(P, r);
+        // and the velocity record is read without waiting on r2.  Two
+        // phases sum sigma here too, in the form every sigma sum takes.
+        const T r = MP ? pair_r(r2) : root(r2);
+        const KernelWF<T> k = wendland_WF(P, r);
+        if (MP) kahan_add(sig, comp, k.W);
+        const T F = k.F;
         const T drj = q.w;
         const T r0j = MP ? vj.w : P.rho0;
         const T rho_j = r0j + drj;
@@ -631,10 +633,11 @@ __global__ void __launch_bounds__(kBlock)
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
-                         if (MP) kahan_add(sig, comp, wendland_W(P, root(r2)));
+                         const T r = MP ? pair_r(r2) : root(r2);
+                         const KernelWF<T> k = wendland_WF(P, r);
+                         if (MP) kahan_add(sig, comp, k.W);
                          if (!(r2 > T(0))) return;
-                         const T r = root(r2);
-                         const T F = wendland_F(P, r);
+                         const T F = k.F;
                          const T p_w = q.w;
                          const T rho_w = r0i + p_w * P.inv_c2;  // the wall takes i's phase
                          T vd = T(0);
@@ -701,14 +704,15 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     // every visited pair, self included, fluid then walls, as k_density sums it
     T s = T(0), comp = T(0);
     auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
-        kahan_add(s, comp, wendland_W(P, root(r2)));
         // no branch for r = 0 (the particle itself, or a coincident one): with
         // the reciprocal root taken of 1 there, every part of its force carries
         // r or d and adds an exact zero, and the velocity record is read
         // without waiting on r2
-        const T rinv = rsq(r2 > T(0) ? r2 : T(1));
-        const T r = r2 * rinv;
-        const T F = wendland_F(P, r);
+        T rinv;
+        const T r = pair_r(r2, rinv);
+        const KernelWF<T> k = wendland_WF(P, r);
+        kahan_add(s, comp, k.W);
+        const T F = k.F;
         const T drj = q.w;
         const T r0j = MP ? vj.w : P.rho0;
         const T rho_j = r0j + drj;
@@ -741,10 +745,11 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     if (nw > 0)
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int w, const T d[3], T r2, uint32_t, const Rec<T>& q) {
-                         kahan_add(s, comp, wendland_W(P, root(r2)));
+                         const T r = pair_r(r2);
+                         const KernelWF<T> k = wendland_WF(P, r);
+                         kahan_add(s, comp, k.W);
                          if (!(r2 > T(0))) return;
-                         const T r = root(r2);
-                         const T F = wendland_F(P, r);
+                         const T F = k.F;
                          const T p_w = q.w;
                          const T rho_w = r0i + p_w * P.inv_c2;  // the wall takes i's phase
                          const T sum = rho_i + rho_w;
