@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
         for (int k = 0; k < D; ++k) vd += (vi[k] - vjk[k]) * d[k];
         const T qq = rcp(rho_j * (rho_i + rho_j));
-        const T term = F * qq * (rho_j * vd + P.c2 * (dri - drj) * r * P.cinv);
+        const T term = F * qq * (rho_j * vd + P.c * (dri - drj) * r);  // c^2 (rho_i - rho_j) r / c
         sum += MP ? r0j * term : term;  // m_j = rho0_j dx^d
     };
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
@@ -699,6 +699,7 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     const T rho_i = r0i + dri;
     const T p_i = P.c2 * dri;
     const T inv_rho_i = T(1) / rho_i;
+    const T m_rho_i = P.m * inv_rho_i;  // m_j / rho_i of a single-phase pair
     T A[3] = {0, 0, 0};
     // sigma of these positions, the next density update's sum (Eq. (4)):
     // every visited pair, self included, fluid then walls, as k_density sums it
@@ -730,11 +731,15 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
         const T sum = rho_i + rho_j;
         const T qq = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
         const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * qq);
-        const T mj = MP ? r0j * P.vol : P.m;
-        const T coef = mj * F * (sum * qq) * inv_rho_i;  // m_j F/(rho_i rho_j)
+        const T mr = MP ? r0j * P.vol * inv_rho_i : m_rho_i;
+        const T coef = mr * F * (sum * qq);  // m_j F/(rho_i rho_j)
         const T visc = P.mu2 * r2 * rcp(r2 + P.eta2);
+        const T cv = coef * visc, cp = T(-2) * coef * pstar;
 #pragma unroll
-        for (int k = 0; k < D; ++k) A[k] += coef * (visc * dv[k] - T(2) * pstar * d[k]);
+        for (int k = 0; k < D; ++k) {
+            A[k] += cv * dv[k];
+            A[k] += cp * d[k];
+        }
     };
     auto fluid_g = [&](int j, const T d[3], T r2, uint32_t code, const Rec<T>& q) {
         fluid(j, d, r2, code, q, ld4(vk, j));
