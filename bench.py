@@ -66,7 +66,7 @@ WALL_BC_BYTES_WALL = 44
 # kernel sources whose SHA-256 is recorded; once those change the traffic is
 # reported as null until the counters are taken again.
 TRAFFIC = {
-    "sources_sha256": "1466d424c8d073d89fa37cdefbc57179f0ac63c8c47dc204ade5851e47768146",
+    "sources_sha256": "230a3970567c3769056f0beceedc4fb88214c46e62863a402dcb5ae57e40aa16",
     "momentum": 2055.0e6 + 269.2e6,
     "continuity": 2080.3e6 + 139.7e6,
 }

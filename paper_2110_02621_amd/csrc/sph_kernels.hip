@@ -513,6 +513,11 @@ __global__ void __launch_bounds__(kBlock)
               const Rec<T>* __restrict__ vk, Rec<T>* __restrict__ wk, T* __restrict__ pw) {
     const int64_t w = global_index();
     if (w >= nw) return;
+    if (nf == 0 || (LWF.mask && LWF.count[w] == 0)) {  // no fluid neighbour: Eq. (12) gives 0
+        pw[w] = T(0);
+        wk[w].w = T(0);
+        return;
+    }
     int c[3];
     cell_of(P, wkey[w], c);
     const Rec<T> me = wk[w];
