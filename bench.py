@@ -142,6 +142,20 @@ def measured_traffic(kernel):
     return TRAFFIC.get(kernel)
 
 
+def adjoint_timing(scenes, args, precision):
+    """J, dJ/dtheta and the forward and backward times of the differentiable
+    2-D dam break with a `precision` forward (after a short warm-up run)."""
+    from paper_2110_02621_amd import adjoint
+    sc4 = scenes.dam_break_2d(dx=args.adj_dx, steps=args.adj_steps)
+    adjoint.probe_gradient(scenes.dam_break_2d(dx=args.adj_dx, steps=2 * args.adj_K),
+                           precision=precision, K=args.adj_K)  # warm-up (kernels, allocator)
+    r = adjoint.probe_gradient(sc4, precision=precision, K=args.adj_K, return_timings=True)
+    return dict(workload=f"2-D dam break dx={args.adj_dx} m ({sc4.n_fluid} fluid + {sc4.n_wall} wall), "
+                         f"{args.adj_steps} steps, checkpoint every {args.adj_K}",
+                t_forward_s=r["t_forward"], t_backward_s=r["t_backward"],
+                ratio=r["t_backward"] / r["t_forward"], J=r["J"], grad=r["grad"])
+
+
 def copy_rate(torch, gib=2.0, reps=10):
     """Bytes read plus written per second of a plain device-to-device copy
     of `gib` GiB (the HBM rate a streaming kernel reaches in practice)."""
@@ -183,13 +197,10 @@ def main():
     from paper_2110_02621_amd import scenes, solver
 
     if args.adjoint_only:
-        from paper_2110_02621_amd import adjoint
-        sca = scenes.dam_break_2d(dx=args.adj_dx, steps=args.adj_steps)
-        adjoint.probe_gradient(scenes.dam_break_2d(dx=args.adj_dx, steps=2 * args.adj_K),
-                               precision="f32", K=args.adj_K)  # warm-up
-        r = adjoint.probe_gradient(sca, precision="f32", K=args.adj_K, return_timings=True)
-        print(json.dumps(dict(t_forward_s=r["t_forward"], t_backward_s=r["t_backward"],
-                              ratio=r["t_backward"] / r["t_forward"], grad=r["grad"])), flush=True)
+        adj = adjoint_timing(scenes, args, "f32")
+        adj["f64"] = adjoint_timing(scenes, args, "f64")
+        adj["f64"].pop("workload")
+        print(json.dumps(adj), flush=True)
         return
 
     if args.sloshing_only:
@@ -344,16 +355,14 @@ def main():
 
     adj = None
     if not args.no_adjoint:
-        from paper_2110_02621_amd import adjoint
-        sc4 = scenes.dam_break_2d(dx=args.adj_dx, steps=args.adj_steps)
-        adjoint.probe_gradient(scenes.dam_break_2d(dx=args.adj_dx, steps=2 * args.adj_K),
-                               precision="f32", K=args.adj_K)  # warm-up (kernels, allocator)
-        r = adjoint.probe_gradient(sc4, precision="f32", K=args.adj_K, return_timings=True)
-        adj = dict(workload=f"2-D dam break dx={args.adj_dx} m ({sc4.n_fluid} fluid + {sc4.n_wall} wall), "
-                            f"{args.adj_steps} steps, checkpoint every {args.adj_K}",
-                   t_forward_s=r["t_forward"], t_backward_s=r["t_backward"],
-                   ratio=r["t_backward"] / r["t_forward"], J=r["J"], grad=r["grad"])
-        print(f"[bench] adjoint fwd {r['t_forward']:.3f} s bwd {r['t_backward']:.3f} s grad {r['grad']}",
+        adj = adjoint_timing(scenes, args, "f32")
+        print(f"[bench] adjoint fwd {adj['t_forward_s']:.3f} s bwd {adj['t_backward_s']:.3f} s grad {adj['grad']}",
+              file=sys.stderr, flush=True)
+        # the same with an FP64 forward (its gradient agrees with FP64 central
+        # differences to ~3e-5 at this size, the FP32 one to ~1e-3)
+        adj["f64"] = adjoint_timing(scenes, args, "f64")
+        adj["f64"].pop("workload")
+        print(f"[bench] adjoint f64 fwd {adj['f64']['t_forward_s']:.3f} s bwd {adj['f64']['t_backward_s']:.3f} s",
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
