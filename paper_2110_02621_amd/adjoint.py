@@ -140,17 +140,22 @@ def recompute_segment(S, pool, start_state, nsteps, first_frame_extra=None):
     return [FramePool.struct(f) for f in pool.frames[:nsteps + 1]]
 
 
-def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", return_timings=False):
-    """J and dJ/dtheta for theta = (mu, gamma_p, c0, H) of `scene` over
-    `steps` steps (default scene.steps), checkpoints every K steps."""
-    import time
+class Tape:
+    """What the forward leaves for the backward: the solver (walls, probe,
+    buffers), the checkpoints (state every K steps, device copies), the
+    initial half-step velocity and wall pressure, and J."""
+
+    def __init__(self, S, scene, K, steps, ckpts, init_extra, J):
+        self.S, self.scene, self.K, self.steps = S, scene, K, steps
+        self.ckpts, self.init_extra, self.J = ckpts, init_extra, J
+
+
+def forward(scene, precision="f32", K=50, steps=None, device="cuda") -> Tape:
+    """Run `steps` steps (default scene.steps) of `scene`, keeping a
+    checkpoint every K steps; J is read at the end."""
     steps = scene.steps if steps is None else steps
     S = Solver(scene, precision, device=device, probe=True, keep_sigma=True)
-    L = S.lib
-    _declare(L)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    # forward with checkpoints
+    _declare(S.lib)
     init_extra = dict(vh=_cur(S)["vel"].clone(), pw=S.t["pw"].clone())
     ckpts = []
     done = 0
@@ -160,16 +165,21 @@ def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", retu
         S.step(k)
         done += k
     J = S.diag()["J"]
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    # backward
+    return Tape(S, scene, K, steps, ckpts, init_extra, J)
+
+
+def backward(tape: Tape):
+    """dJ/dtheta (float64 device tensor [mu, gamma_p, c0, H]) from a tape:
+    every segment, last first, is recomputed from its checkpoint with its
+    frames recorded and then stepped backward; the initial state last."""
+    S, scene, K, steps = tape.S, tape.scene, tape.K, tape.steps
+    L = S.lib
     nf, nw, dim = scene.n_fluid, scene.n_wall, scene.dim
-    dev = S.device
-    f64 = dict(dtype=torch.float64, device=dev)
+    f64 = dict(dtype=torch.float64, device=S.device)
     A = {k: torch.zeros((dim, nf) if k != "rhob" else (nf,), **f64) for k in ("xb", "vb", "rhob", "ab")}
-    theta = torch.zeros(abi.SPH_DIAG_LEN, **f64)[:4]
+    theta = torch.zeros(4, **f64)
     wb = int(L.sph_adjoint_work_bytes(C.byref(S.desc), nf, nw))
-    work = torch.zeros(wb + 256, dtype=torch.uint8, device=dev)
+    work = torch.zeros(wb + 256, dtype=torch.uint8, device=S.device)
     adj = Adjoint()
     adj.xb, adj.vb, adj.rhob, adj.ab = (_p(A[k]).value for k in ("xb", "vb", "rhob", "ab"))
     adj.theta = _p(theta).value
@@ -177,23 +187,35 @@ def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", retu
     adj.work_bytes = wb
     stream = S._stream()
     pool = FramePool(S, min(K, steps) + 1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
     check(L.sph_adjoint_zero(C.byref(S.desc), C.byref(S.buf), C.byref(adj), stream), "sph_adjoint_zero")
-    for seg in reversed(range(len(ckpts))):
-        start, st = ckpts[seg]
+    for seg in reversed(range(len(tape.ckpts))):
+        start, st = tape.ckpts[seg]
         k = min(K, steps - start)
-        structs = recompute_segment(S, pool, st, k, init_extra if start == 0 else None)
+        structs = recompute_segment(S, pool, st, k, tape.init_extra if start == 0 else None)
         for n in reversed(range(k)):
             check(L.sph_step_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[n]),
                                  C.byref(structs[n + 1]), C.byref(adj), stream), "sph_step_bwd")
         if start == 0:
             check(L.sph_init_bwd(C.byref(S.desc), C.byref(S.buf), C.byref(structs[0]), float(scene.H),
                                  C.byref(adj), stream), "sph_init_bwd")
+    return theta
+
+
+def probe_gradient(scene, precision="f32", K=50, steps=None, device="cuda", return_timings=False):
+    """J and dJ/dtheta for theta = (mu, gamma_p, c0, H) of `scene` over
+    `steps` steps (default scene.steps), checkpoints every K steps."""
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tape = forward(scene, precision, K, steps, device)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    theta = backward(tape)
     grad = theta.cpu().numpy().copy()
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t1
-    out = dict(J=J, grad=dict(zip(THETA_NAMES, grad.tolist())), status=S.status())
+    out = dict(J=tape.J, grad=dict(zip(THETA_NAMES, grad.tolist())), status=tape.S.status())
     if return_timings:
         out["t_forward"] = t_fwd
         out["t_backward"] = t_bwd
@@ -211,17 +233,23 @@ def scene_for(theta, base="dam_break_2d", **kw):
 class ProbeFunctional(torch.autograd.Function):
     """J(theta) of the 2-D dam break with its hand-written adjoint.
 
-    forward(theta: float64 tensor [mu, gamma_p, c0, H], precision, K, scene kwargs)"""
+    forward(theta: float64 tensor [mu, gamma_p, c0, H], precision, K, scene
+    kwargs) runs the checkpointed forward only and keeps its tape on ctx;
+    backward runs the adjoint (recomputation and backward kernels) once and
+    releases the tape."""
 
     @staticmethod
     def forward(ctx, theta, precision="f32", K=50, scene_kw=None):
         sc = scene_for(theta.detach().cpu().numpy(), **(scene_kw or {}))
-        r = probe_gradient(sc, precision=precision, K=K)
-        g = torch.tensor([r["grad"][n] for n in THETA_NAMES], dtype=torch.float64)
-        ctx.save_for_backward(g)
-        return torch.tensor(r["J"], dtype=torch.float64)
+        tape = forward(sc, precision=precision, K=K)
+        ctx.tape = tape
+        return torch.tensor(tape.J, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, gJ):
-        (g,) = ctx.saved_tensors
+        tape = ctx.tape
+        if tape is None:
+            raise RuntimeError("ProbeFunctional: backward called twice on one forward")
+        g = backward(tape)
+        ctx.tape = None
         return gJ * g.to(gJ.device), None, None, None

@@ -188,35 +188,57 @@ def test_adjoint_penalty_scene_fp64(adj):
     compare(g, fd, th, 1e-4, "jet f64")
 
 
-def test_adjoint_fp32_matches_oracle_finite_differences(adj):
-    # FP32 forward, FP64 gradient accumulation, against FP64 central
-    # differences of the oracle with a relative step of 1e-4.
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_penalty_scene_matches_oracle_finite_differences(adj, prec):
+    # The same impact against FP64 central differences of the oracle: the
+    # non-zero dJ/dgamma_p (Eqs. (13)-(15)) end to end, with the forward in
+    # FP64 and in FP32 (the gradient accumulated in FP64 either way).
+    sc0 = scenes.wall_jet_2d()
+    th = np.array([sc0.mu, sc0.gamma_p, sc0.c0, sc0.H])
+    steps = sc0.steps
+    sc = make("jet", th, steps=steps)
+    print(f"[adj-jet-oracle] {prec} nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
+    fd = fd_oracle("jet", th, steps)
+    assert abs(fd[1]) > 1e-3 * abs(fd[2] * th[2]) / th[1]
+    r = adj.probe_gradient(sc, precision=prec, K=50)
+    g = np.array([r["grad"][n] for n in NAMES])
+    compare(g, fd, th, 1e-4 if prec == "f64" else 1e-3, f"jet {prec} vs oracle")
+
+
+def test_adjoint_matches_oracle_finite_differences(adj):
+    # The benchmark's adjoint: FP64 forward and FP64 backward, against FP64
+    # central differences of the oracle with a relative step of 1e-4 (mu:
+    # 1e-1, see the header).
     kw = dict(dx=0.02)
     th = theta0(scenes.dam_break_2d(**kw))
     steps = 100
     sc = make("dam", th, steps=steps, **kw)
-    print(f"[adj32] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
-    r = adj.probe_gradient(sc, precision="f32", K=25)
-    g = np.array([r["grad"][n] for n in NAMES])
+    print(f"[adj] nf={sc.n_fluid} nw={sc.n_wall} probe={len(sc.probe)}", flush=True)
     fd = fd_oracle("dam", th, steps, kw=kw)
     P = O.params_from_scene(sc)
     st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, probe=sc.probe).step(steps)
-    print(f"  J gpu {r['J']:.9e} oracle {st.J:.9e}", flush=True)
-    assert abs(r["J"] - st.J) <= 1e-4 * abs(st.J)
-    # mu acts through the viscous term, a second difference of the velocity
-    # field: in an FP32 forward its relative error is ~ eps32 (L/dx)^2 ~ 1e-3
-    # here, which bounds any FP32 gradient with respect to mu; the FP64 run
-    # below pins mu tightly.
-    compare(g, fd, th, (5e-3, 1e-3, 1e-3, 1e-3), "dam f32 vs oracle")
     r64 = adj.probe_gradient(sc, precision="f64", K=25)
     g64 = np.array([r64["grad"][n] for n in NAMES])
-    compare(g64, fd, th, 2e-5, "dam f64 vs oracle")
+    print(f"  J gpu {r64['J']:.12e} oracle {st.J:.12e}", flush=True)
+    assert abs(r64["J"] - st.J) <= 1e-9 * abs(st.J)
+    compare(g64, fd, th, 1e-4, "dam f64 vs oracle")
+    # The FP32 forward (FP64 accumulation) gives the derivative along the
+    # FP32 trajectory: c0, H and gamma_p within 1e-3.  mu acts through the
+    # viscous term, a second difference of the velocity field, whose FP32
+    # rounding noise is amplified by ~(L/dx)^2: its floor is a few 1e-3 (the
+    # measured error is printed and recorded with the design notes).
+    r = adj.probe_gradient(sc, precision="f32", K=25)
+    g = np.array([r["grad"][n] for n in NAMES])
+    print(f"  J f32 {r['J']:.9e} oracle {st.J:.9e}", flush=True)
+    assert abs(r["J"] - st.J) <= 1e-4 * abs(st.J)
+    compare(g, fd, th, (5e-3, 1e-3, 1e-3, 1e-3), "dam f32 vs oracle")
 
 
 def test_autograd_function(adj):
     import torch
     th = torch.tensor(theta0(scenes.dam_break_2d(dx=0.04)), dtype=torch.float64, requires_grad=True)
     J = adj.ProbeFunctional.apply(th, "f64", 10, dict(dx=0.04, steps=20))
+    assert th.grad is None
     J.backward()
     assert th.grad is not None and torch.isfinite(th.grad).all()
     sc = make("dam", th.detach().numpy(), dx=0.04, steps=20)
