@@ -15,7 +15,8 @@
  *   - Every pointer inside sph_buffers and every array argument marked
  *     "device" is a device pointer owned by the caller.  The library never
  *     allocates, frees or keeps a pointer between calls, and holds no
- *     global state.  Scratch memory is passed in (sph_scratch_bytes).
+ *     global state, with one exception: the fixed device workspace of
+ *     sph_diag_noalloc.  Scratch memory is passed in (sph_scratch_bytes).
  *   - T is float when desc->precision == SPH_F32 and double for SPH_F64;
  *     "T[dim][n]" means dim arrays of n values of T, one after the other
  *     (structure of arrays: component k of particle i at index k*n + i).
@@ -26,8 +27,8 @@
  *     enqueue work and return; data-dependent faults are counted in the
  *     device status words, to be read after synchronising.
  *   - Return codes are synchronous argument, configuration or launch errors
- *     (SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH).  No call
- *     aborts or prints.
+ *     (SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH, and
+ *     SPH_ERR_CAPACITY from sph_diag_noalloc).  No call aborts or prints.
  *
  * Per-step schedule (sph_step runs exactly this):
  *   sph_density -> sph_build_cells -> sph_wall_bc -> sph_forces(CONTINUITY)
@@ -60,7 +61,9 @@ extern "C" {
 #define SPH_ERR_ARG 1    /* null pointer, negative size, size mismatch, bad flag */
 #define SPH_ERR_CONFIG 2 /* dim not 2 or 3, precision unknown, dt above the CFL bound of
                             Eqs. (23)-(24), grid too large, L_c < 2h, bad motion */
-#define SPH_ERR_LAUNCH 3 /* a kernel launch failed (hipGetLastError after the launch) */
+#define SPH_ERR_LAUNCH 3 /* a kernel launch failed (hipGetLastError after the launch), or
+                            sph_diag_noalloc could not look up its device workspace */
+#define SPH_ERR_CAPACITY 4 /* sph_diag_noalloc: more fluid particles than its fixed workspace holds */
 
 #define SPH_F32 0
 #define SPH_F64 1
@@ -270,6 +273,24 @@ int sph_step(const sph_desc *desc, sph_buffers *buf, int nsteps, void *stream);
  * deterministic order; fixed-frame positions and velocities at nstep dt).  Non-finite values are counted in
  * SPH_STATUS_NONFINITE.  The probe entry and the step count are kept. */
 int sph_diag(const sph_desc *desc, sph_buffers *buf, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): sph_diag
+ * without its scratch argument.  Computes exactly what sph_diag computes,
+ * with the same kernels and the same summation order (bit-identical
+ * results); b->scratch and b->scratch_bytes are not read, every other
+ * buffer is as for sph_diag.  The per-block partial sums live in a device
+ * array of SPH_DIAG_NOALLOC_BYTES that the library holds on each GPU it
+ * runs on until the process ends; the call allocates and frees nothing.
+ * Every call on one GPU uses that GPU's single array: calls that overlap
+ * on one GPU (different streams or host threads) race and must be
+ * serialised by the caller.  The partials are written in full by each call
+ * before they are read, so nothing needs clearing between calls.
+ * Returns SPH_ERR_CAPACITY when n_fluid > SPH_DIAG_NOALLOC_MAX_FLUID, and
+ * SPH_ERR_LAUNCH if the workspace's device address cannot be obtained. */
+#define SPH_DIAG_NOALLOC_BYTES (4u << 20)          /* 4 MiB per GPU */
+#define SPH_DIAG_NOALLOC_MAX_FLUID ((int64_t)1 << 24) /* 65,536 blocks x 256 particles x 8 doubles */
+int sph_diag_noalloc(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Copies the fluid state out in particle-id order as doubles (device
  * arrays, any may be NULL): pos double[dim][n_fluid] absolute positions,

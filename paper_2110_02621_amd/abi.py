@@ -11,16 +11,18 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsph.so")
 
-SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH = 0, 1, 2, 3
+SPH_OK, SPH_ERR_ARG, SPH_ERR_CONFIG, SPH_ERR_LAUNCH, SPH_ERR_CAPACITY = 0, 1, 2, 3, 4
 SPH_F32, SPH_F64 = 0, 1
 SPH_CONTINUITY, SPH_MOMENTUM, SPH_NO_KICK = 1, 2, 4
 SPH_STATUS_OUT_OF_GRID, SPH_STATUS_FAST, SPH_STATUS_NONFINITE, SPH_STATUS_LIST_OVERFLOW = 0, 1, 2, 3
 SPH_STATUS_LEN = 4
 SPH_DIAG_MASS, SPH_DIAG_MOM, SPH_DIAG_EKIN, SPH_DIAG_EPOT = 0, 1, 4, 5
 SPH_DIAG_VMAX, SPH_DIAG_PROBE, SPH_DIAG_STEPS, SPH_DIAG_LEN = 6, 7, 8, 16
+SPH_DIAG_NOALLOC_BYTES, SPH_DIAG_NOALLOC_MAX_FLUID = 4 << 20, 1 << 24
 
 EXPORTED = ["sph_configure", "sph_scratch_bytes", "sph_init", "sph_build_cells", "sph_density",
-            "sph_wall_bc", "sph_forces", "sph_step", "sph_diag", "sph_export", "sph_export_walls",
+            "sph_wall_bc", "sph_forces", "sph_step", "sph_diag", "sph_diag_noalloc", "sph_export",
+            "sph_export_walls",
             "sph_neighbours", "sph_strerror",
             "sph_adjoint_work_bytes", "sph_adjoint_zero", "sph_forces_bwd", "sph_wall_bc_bwd",
             "sph_density_bwd", "sph_step_bwd", "sph_init_bwd", "sph_step_frame"]
@@ -75,7 +77,7 @@ def load():
     L.sph_scratch_bytes.argtypes = [dp, C.c_int64, C.c_int64]
     L.sph_scratch_bytes.restype = C.c_size_t
     L.sph_init.argtypes = [dp, bp, vp, vp, vp, vp, vp]
-    for name in ("sph_build_cells", "sph_density", "sph_wall_bc", "sph_diag"):
+    for name in ("sph_build_cells", "sph_density", "sph_wall_bc", "sph_diag", "sph_diag_noalloc"):
         getattr(L, name).argtypes = [dp, bp, vp]
     L.sph_forces.argtypes = [dp, bp, C.c_uint, vp]
     L.sph_step.argtypes = [dp, bp, C.c_int, vp]

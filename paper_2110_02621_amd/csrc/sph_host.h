@@ -204,13 +204,12 @@ inline int64_t max_particles(const sph_desc* d) {
     return d->precision == SPH_F32 ? (int64_t{1} << 28) - 1 : (int64_t{1} << 27) - 1;
 }
 
-inline int check_buf(const sph_desc* d, const sph_buffers* b) {
+// Every buffer of the state and the outputs, scratch aside.
+inline int check_state(const sph_desc* d, const sph_buffers* b) {
     if (!b) return SPH_ERR_ARG;
     if (b->n_fluid < 0 || b->n_wall < 0) return SPH_ERR_ARG;
     if (b->n_fluid > max_particles(d) || b->n_wall > max_particles(d)) return SPH_ERR_ARG;
     if (b->sel_vel < 0 || b->sel_vel > 1 || b->sel_rho < 0 || b->sel_rho > 1) return SPH_ERR_ARG;
-    if (!b->scratch || b->scratch_bytes < sph_scratch_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
-    if (((uintptr_t)b->scratch & 255) != 0) return SPH_ERR_ARG;
     if (!b->status || !b->diag || !b->fstart || !b->wstart) return SPH_ERR_ARG;
     if (b->n_fluid > 0) {
         for (int c = 0; c < 2; ++c)
@@ -223,6 +222,14 @@ inline int check_buf(const sph_desc* d, const sph_buffers* b) {
     if (masks) {  // all three or none
         if (!b->nbr_ff || !b->nbr_fw || !b->nbr_wf || !b->cnt_ff || !b->cnt_fw || !b->cnt_wf) return SPH_ERR_ARG;
     }
+    return SPH_OK;
+}
+
+inline int check_buf(const sph_desc* d, const sph_buffers* b) {
+    const int rc = check_state(d, b);
+    if (rc) return rc;
+    if (!b->scratch || b->scratch_bytes < sph_scratch_bytes(d, b->n_fluid, b->n_wall)) return SPH_ERR_ARG;
+    if (((uintptr_t)b->scratch & 255) != 0) return SPH_ERR_ARG;
     return SPH_OK;
 }
 

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "sph.h"
@@ -1339,10 +1340,11 @@ int step_frame_t(const sph_desc* d, sph_buffers* b, void* sigma_cur, sph_frame* 
     return SPH_OK;
 }
 
+// The reductions of sph_diag with the per-block partials (kDiagVals doubles
+// per block of kBlock particles) in `part`.
 template <typename T, int D>
-int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
+int diag_impl(const sph_desc* d, sph_buffers* b, double* part, hipStream_t st) {
     const int64_t nf = b->n_fluid;
-    const Scratch s = layout(d, nf, b->n_wall, b->scratch);
     const int nb = nf > 0 ? grid_for(nf) : 0;
     if (nb > 0) {
         DiagC K;
@@ -1352,12 +1354,22 @@ int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
         for (int k = 0; k < 3; ++k) K.g[k] = d->g[k];
         hipLaunchKernelGGL((k_diag_partial<T, D>), dim3(nb), dim3(kBlock), 0, st, make_par<T>(d),
                            make_grid_at(d, b->nstep), K, nf, b->key[0], b->pid[0], (const T*)b->off[0],
-                           (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], s.part);
+                           (const T*)b->vel[b->sel_vel], (const T*)b->rho[b->sel_rho], part);
         SPH_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, st, s.part, nb, b->diag, b->status);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, st, part, nb, b->diag, b->status);
     SPH_LAUNCH_CHECK();
     return SPH_OK;
+}
+
+template <typename T, int D>
+int diag_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
+    return diag_impl<T, D>(d, b, layout(d, b->n_fluid, b->n_wall, b->scratch).part, st);
+}
+
+template <typename T, int D>
+int diag_static_t(const sph_desc* d, sph_buffers* b, double* part, hipStream_t st) {
+    return diag_impl<T, D>(d, b, part, st);
 }
 
 template <typename T, int D>
@@ -1402,6 +1414,37 @@ int neighbours_t(const sph_desc* d, const sph_buffers* b, int which, const int64
 #define SPH_DISPATCH(fn, ...)                                                          \
     (d->precision == SPH_F32 ? (d->dim == 2 ? fn<float, 2>(__VA_ARGS__) : fn<float, 3>(__VA_ARGS__)) \
                              : (d->dim == 2 ? fn<double, 2>(__VA_ARGS__) : fn<double, 3>(__VA_ARGS__)))
+
+}  // namespace
+
+// Workspace of sph_diag_noalloc: the per-block partials of the reductions,
+// in a device array that the library holds for the life of the process
+// (one copy per GPU), so that call allocates nothing.  Host code never
+// passes this name to a kernel (on the host it is only a stand-in for the
+// symbol): it passes the address hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[SPH_DIAG_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// first call made with that device current).
+int static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPH_ERR_LAUNCH;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPH_ERR_LAUNCH;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return SPH_OK;
+}
 
 }  // namespace
 
@@ -1541,6 +1584,19 @@ int sph_diag(const sph_desc* d, sph_buffers* b, void* stream) {
     return SPH_DISPATCH(diag_t, d, b, st);
 }
 
+int sph_diag_noalloc(const sph_desc* d, sph_buffers* b, void* stream) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    rc = check_state(d, b);  // b->scratch is not read
+    if (rc) return rc;
+    if (b->n_fluid > SPH_DIAG_NOALLOC_MAX_FLUID) return SPH_ERR_CAPACITY;
+    void* part = nullptr;
+    rc = static_scratch(&part);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    return SPH_DISPATCH(diag_static_t, d, b, (double*)part, st);
+}
+
 int sph_export(const sph_desc* d, const sph_buffers* b, double* pos, double* vel, double* rho,
                double* acc, void* stream) {
     SPH_ENTRY_CHECKS();
@@ -1566,7 +1622,8 @@ const char* sph_strerror(int code) {
         case SPH_OK: return "ok";
         case SPH_ERR_ARG: return "invalid argument (null pointer, size or flag)";
         case SPH_ERR_CONFIG: return "invalid configuration (dim, precision, grid, or dt above the CFL bound)";
-        case SPH_ERR_LAUNCH: return "kernel launch failed";
+        case SPH_ERR_LAUNCH: return "a HIP call failed (kernel launch or device symbol lookup)";
+        case SPH_ERR_CAPACITY: return "more fluid particles than the fixed device workspace of sph_diag_noalloc holds";
         default: return "unknown error";
     }
 }

@@ -36,12 +36,19 @@ def test_binding_mirrors_header():
     assert sorted(abi.EXPORTED) == declared()
     text = open(HEADER).read()
     for name, val in [("SPH_OK", abi.SPH_OK), ("SPH_ERR_ARG", abi.SPH_ERR_ARG),
-                      ("SPH_ERR_CONFIG", abi.SPH_ERR_CONFIG), ("SPH_F64", abi.SPH_F64),
+                      ("SPH_ERR_CONFIG", abi.SPH_ERR_CONFIG), ("SPH_ERR_LAUNCH", abi.SPH_ERR_LAUNCH),
+                      ("SPH_ERR_CAPACITY", abi.SPH_ERR_CAPACITY), ("SPH_F64", abi.SPH_F64),
                       ("SPH_CONTINUITY", abi.SPH_CONTINUITY), ("SPH_MOMENTUM", abi.SPH_MOMENTUM),
                       ("SPH_NO_KICK", abi.SPH_NO_KICK), ("SPH_DIAG_LEN", abi.SPH_DIAG_LEN),
                       ("SPH_DIAG_PROBE", abi.SPH_DIAG_PROBE), ("SPH_STATUS_LEN", abi.SPH_STATUS_LEN)]:
         m = re.search(rf"#define {name} (\d+)", text)
         assert m and int(m.group(1)) == val, name
+    assert re.search(r"#define SPH_DIAG_NOALLOC_BYTES \(4u << 20\)", text) and abi.SPH_DIAG_NOALLOC_BYTES == 4 << 20
+    assert re.search(r"#define SPH_DIAG_NOALLOC_MAX_FLUID \(\(int64_t\)1 << 24\)", text)
+    assert abi.SPH_DIAG_NOALLOC_MAX_FLUID == 1 << 24
+    # the partials of the largest accepted input fill the workspace exactly:
+    # one block of 256 particles leaves 8 doubles
+    assert abi.SPH_DIAG_NOALLOC_MAX_FLUID // 256 * 8 * 8 == abi.SPH_DIAG_NOALLOC_BYTES
 
 
 def test_host_configuration_checks():
@@ -106,3 +113,26 @@ def test_particle_count_limits():
             assert fn(ctypes.byref(d), 1000, top) > 0, prec
             assert fn(ctypes.byref(d), top + 1, 1000) == 0, prec
             assert fn(ctypes.byref(d), 1000, top + 1) == 0, prec
+
+
+def test_diag_noalloc_refuses_inputs_beyond_its_workspace():
+    # Host-side checks run before any HIP call: a state larger than the fixed
+    # workspace is refused with SPH_ERR_CAPACITY, a missing buffer with
+    # SPH_ERR_ARG.  The pointers are never dereferenced on these paths.
+    from paper_2110_02621_amd import abi, scenes
+    from paper_2110_02621_amd.solver import make_desc
+    lib = abi.load()
+    d = make_desc(scenes.dam_break_3d(dx=0.02), "f32")
+    b = abi.Buffers()
+    fake = 1 << 20
+    for c in range(2):
+        b.key[c] = b.pid[c] = b.off[c] = b.vel[c] = b.rho[c] = fake
+    b.acc = b.wkey = b.wpid = b.woff = b.pw = b.nrm = b.fstart = b.wstart = fake
+    b.status = b.diag = fake
+    b.n_wall = 10
+    b.n_fluid = abi.SPH_DIAG_NOALLOC_MAX_FLUID + 1
+    assert lib.sph_diag_noalloc(ctypes.byref(d), ctypes.byref(b), None) == abi.SPH_ERR_CAPACITY
+    assert b"workspace" in lib.sph_strerror(abi.SPH_ERR_CAPACITY)
+    b.n_fluid = 1000
+    b.diag = None
+    assert lib.sph_diag_noalloc(ctypes.byref(d), ctypes.byref(b), None) == abi.SPH_ERR_ARG
