@@ -95,6 +95,9 @@ def parse():
                     help="time only the shaken two-phase tank at this dx (kernel profiles of that case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps of the CPU baseline (about 3 s each)")
+    ap.add_argument("--cpu-stride", type=int, default=16,
+                    help="every n-th particle in the one-thread oracle sample")
+    ap.add_argument("--cpu-sample-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--adj-steps", type=int, default=1000, help="steps of the differentiable 2-D dam break")
     ap.add_argument("--adj-dx", type=float, default=0.005)
@@ -175,6 +178,55 @@ def copy_rate(torch, gib=2.0, reps=10):
     return rate
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), as lscpu reports it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_stage_sample(dx, obstacles, stride):
+    """Seconds the FP64 oracle takes for the pair sums of one step (number
+    density, wall pressure, continuity, momentum) of every stride-th fluid
+    and wall particle of the benchmark workload, from its initial state.
+    Run in a child process whose OpenMP thread count is fixed by its
+    environment; prints one JSON line."""
+    import numpy as np
+    import oracle
+    from paper_2110_02621_amd import scenes
+    sc = scenes.dam_break_3d(dx=dx, obstacles=obstacles, seed=0)
+    P = oracle.params_from_scene(sc)
+    q = np.arange(0, sc.n_fluid, stride)
+    qw = np.arange(0, sc.n_wall, stride)
+    pw = np.zeros(sc.n_wall)
+    wn = np.zeros((sc.n_wall, 3))
+    t0 = time.perf_counter()
+    oracle.sigma(P, sc.fluid_x, sc.wall_x, query=q)
+    oracle.wall_pressure(P, sc.wall_x, sc.fluid_x, sc.fluid_rho, query=qw)
+    oracle.continuity(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, pw, query=q)
+    oracle.momentum(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x, pw, wn, query=q)
+    t = time.perf_counter() - t0
+    print(json.dumps(dict(seconds=t, particles=int(len(q) + len(qw)), threads=oracle.num_threads())), flush=True)
+
+
+def cpu_sample_in_child(args, threads):
+    """cpu_stage_sample in a child process with OMP_NUM_THREADS = threads."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-child", "--dx", str(args.dx),
+           "--obstacles", str(args.obstacles), "--cpu-stride", str(args.cpu_stride)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU sample child failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def pair_counts(S):
     """Interacting pairs of the current state: fluid-fluid (self excluded),
     fluid-wall, wall-fluid, and fluid-(fluid+wall) with self."""
@@ -186,6 +238,9 @@ def pair_counts(S):
 
 def main():
     args = parse()
+    if args.cpu_sample_child:  # the oracle's timed sample, in a child process (no GPU)
+        cpu_stage_sample(args.dx, args.obstacles, args.cpu_stride)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the hot path here is "
               "the single-GPU sweep; multi-GPU sharding is design-only.", file=sys.stderr)
@@ -388,8 +443,22 @@ def main():
         cpu = dict(value=n_tot * args.cpu_steps / tcpu, unit="particle-steps/s", cores=oracle.num_threads(),
                    kind="oracle",
                    sample=f"{args.cpu_steps} FP64 oracle step(s) of the full workload "
-                          f"({n_tot} particles), {tcpu:.1f} s (+{tinit:.1f} s initialisation, untimed)")
+                          f"({n_tot} particles), {tcpu:.1f} s (+{tinit:.1f} s initialisation, untimed)",
+                   cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                   host_cpus_usable=len(os.sched_getaffinity(0)))
         print(f"[bench] cpu oracle {tcpu:.1f} s for {args.cpu_steps} step(s)", file=sys.stderr, flush=True)
+        # the pair sums of one step on every stride-th particle, with one
+        # thread and with all of them (child processes)
+        one = cpu_sample_in_child(args, 1)
+        allt = cpu_sample_in_child(args, oracle.num_threads())
+        cpu["one_thread"] = dict(
+            value=one["particles"] / one["seconds"], unit="particle-steps/s", threads=one["threads"],
+            sample=f"FP64 oracle pair sums of one step (number density, wall pressure, continuity, momentum) "
+                   f"on every {args.cpu_stride}th particle ({one['particles']} particles) of the same workload, "
+                   f"{one['seconds']:.1f} s; the same sample with {allt['threads']} threads: "
+                   f"{allt['seconds']:.2f} s ({one['seconds'] / allt['seconds']:.1f}x)")
+        print(f"[bench] cpu oracle sample: 1 thread {one['seconds']:.2f} s, {allt['threads']} threads "
+              f"{allt['seconds']:.2f} s", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,

@@ -225,7 +225,7 @@ size_t sph_scratch_bytes(const sph_desc *desc, int64_t n_fluid, int64_t n_wall);
 int sph_init(const sph_desc *desc, sph_buffers *buf, const double *fpos, const double *fvel,
              const double *frho, const double *wpos, void *stream);
 
-/* Neighbour search, "including sorting algorithms" (Sec. 3, Table 1).
+/* Neighbour search with the sorting of particles by cell (Sec. 3, Table 1).
  * Stable counting sort of the drifted fluid (key[1], off[1], pid[1] and the
  * current velocity and density) by cell key into key[0], off[0], pid[0] and
  * the other velocity/density copy; particles of one cell keep their prior

@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBlock)
             const double Nc = 2.0 * (ri * pj_ + rj * pi_) / Q.c + ri * rj * J * bc;
             th[SPH_THETA_C0] += -2.0 * C * ai * Nc / S;
         });
-        if (nw > 0)
+        if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
             visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
                         [&](int w, const T dT[3], T r2T, uint32_t) {
                 if (!(r2T > T(0))) return;
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(kBlock)
             gr += -L / S + G.F / S * (G.r / Q.c) * (psi_j / (ri * ri) * dp + Psi * Q.c2);
             th[SPH_THETA_C0] += psi_i * G.F * dp * G.r / (rj * S * Q.c2);
         });
-        if (nw > 0)
+        if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
             visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
                         [&](int w, const T dT[3], T r2T, uint32_t) {
                 if (!(r2T > T(0))) return;
@@ -476,6 +476,7 @@ __global__ void __launch_bounds__(kBlock)
         const double rf = Q.rho0 + (double)rho[i];
         const double pf_ = Q.c2 * (double)rho[i];
         double gx[3] = {0, 0, 0}, gr = 0.0;
+        if (!LW.mask || LW.count[i] != 0)  // no wall neighbour: nothing to add
         visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
                     [&](int w, const T dT[3], T r2T, uint32_t) {
             const double lw = lam[w];
@@ -554,7 +555,7 @@ __global__ void __launch_bounds__(kBlock)
         const double s = si + sigbs[j];
         for (int k = 0; k < D; ++k) gx[k] += s * G.F * G.d[k];
     });
-    if (nw > 0)
+    if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
         visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi,
                     [&](int, const T dT[3], T r2T, uint32_t) {
             if (!(r2T > T(0))) return;

@@ -151,6 +151,7 @@ struct Scratch {
     void* vk[2];
     void* wk;
     void* nk;
+    uint8_t* wnear;  // n_cells: 1 when a wall particle lies in the cell's neighbour cells (set by sph_init)
     size_t bytes;
 };
 
@@ -180,6 +181,7 @@ inline Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
     for (int k = 0; k < 2; ++k) s.vk[k] = take(4 * ts * (size_t)nf);
     s.wk = take(4 * ts * (size_t)nw);
     s.nk = take(4 * ts * (size_t)nw);
+    s.wnear = (uint8_t*)take((size_t)d->n_cells);
     s.bytes = o;
     return s;
 }

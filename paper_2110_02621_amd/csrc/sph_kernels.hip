@@ -51,7 +51,7 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort by cell key (neighbour search "including sorting", Sec. 3).
+// Counting sort by cell key (the sorting part of the neighbour search, Sec. 3, Table 1).
 //   1. histogram: slot_i = atomic fetch-add on count[key_i] (the count per
 //      cell is exact; the slot order inside a cell is arbitrary);
 //   2. exclusive scan of the counts -> cell start table;
@@ -251,6 +251,27 @@ __global__ void __launch_bounds__(kBlock)
     if (w >= nw) return;
     wk[w] = Rec<T>{woff[w], woff[nw + w], D == 3 ? woff[2 * nw + w] : T(0), T(0)};
     nk[w] = Rec<T>{nrm[w], nrm[nw + w], D == 3 ? nrm[2 * nw + w] : T(0), T(0)};
+}
+
+// Cells with at least one wall particle among their 27 (3-D) or 9 (2-D)
+// neighbour cells (the walls are sorted once, so this is built once).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_wall_near(Par<T> P, int64_t n_cells, const int32_t* __restrict__ wstart, uint8_t* __restrict__ near) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_cells) return;
+    int c[3];
+    cell_of(P, (int)k, c);
+    const int x0 = max(c[0] - 1, 0), x1 = min(c[0] + 1, P.nx - 1);
+    bool any = false;
+    for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = c[1] + dy, z = c[2] + dz;
+            if (y < 0 || y >= P.ny || z < 0 || z >= (D == 3 ? P.nz : 1)) continue;
+            const int row = P.nx * (y + P.ny * z);
+            any = any || wstart[row + x1 + 1] > wstart[row + x0];
+        }
+    near[k] = any ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +475,8 @@ __global__ void __launch_bounds__(kBlock)
     } else {
         auto addW = [&](int, const T*, T r2, uint32_t) { kahan_add(s, comp, wendland_W(P, pair_r(r2))); };
         visit<T, D>(P, LF, i, fstart, o0, o1, o2, c, oi, addW);
-        if (nw > 0) visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
+        if (nw > 0 && (!LW.mask || LW.count[i] != 0))
+            visit<T, D>(P, LW, i, wstart, woff, woff + nw, woff + 2 * nw, c, oi, addW);
     }
     if (sigma_out) sigma_out[i] = s;
     // Eq. (17) in deviations from rho0: rho_s - rho0 = rho0 (sigma - sigma0)/sigma0.
@@ -636,7 +658,7 @@ __global__ void __launch_bounds__(kBlock)
     fluid_sweep<kStageC, T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid,
                                fluid_g);
     if (!act) return;
-    if (nw > 0)
+    if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
                          const T r = MP ? pair_r(r2) : root(r2);
@@ -753,7 +775,7 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     fluid_sweep<kStage, T, D>(P, LF, fstart, pk, vk, key, stage, block_mode, SB, act, ib, nf, i, c, oi, fluid,
                               fluid_g);
     if (!act) return;
-    if (nw > 0)
+    if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
         visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
                      [&](int w, const T d[3], T r2, uint32_t, const Rec<T>& q) {
                          const T r = pair_r(r2);
@@ -815,16 +837,21 @@ __global__ void __launch_bounds__(kBlock)
     k_masks_fluid(Par<T> P, int64_t nf, int64_t nw, const int32_t* __restrict__ key,
                   const Rec<T>* __restrict__ pk, const int32_t* __restrict__ fstart,
                   const Rec<T>* __restrict__ wk, const int32_t* __restrict__ wstart,
-                  uint64_t* __restrict__ mf, int32_t* __restrict__ cf, uint64_t* __restrict__ mw,
-                  int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
+                  const uint8_t* __restrict__ wnear, uint64_t* __restrict__ mf, int32_t* __restrict__ cf,
+                  uint64_t* __restrict__ mw, int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
     __shared__ Rec<T> stage_p[kBlock / 64][kStageM];
     const int64_t i0 = global_index();
     const int64_t ib = i0 - (threadIdx.x & 63);
     if (ib >= nf) return;  // the whole wave is past the end
     const bool act = i0 < nf;
     const int64_t i = act ? i0 : nf - 1;
+    const int k = key[i];
+    // cells without a wall particle among their neighbour cells (wnear,
+    // built once at init) have no wall candidates: every wall row would be
+    // skipped and no word written
+    const bool near = nw > 0 && wnear[k] != 0;
     int c[3];
-    cell_of(P, key[i], c);
+    cell_of(P, k, c);
     const Rec<T> me = pk[i];
     const T oi[3] = {me.x, me.y, me.z};
     const WaveSpan S = wave_span(P, key, ib, nf);
@@ -837,7 +864,7 @@ __global__ void __launch_bounds__(kBlock)
     if (!act) return;
     cf[i] = n;
     int m = 0;
-    if (nw > 0) m = build_mask<T, D>(P, wstart, PackSrc<T>{wk}, c, oi, mw, nf, i);
+    if (near) m = build_mask<T, D>(P, wstart, PackSrc<T>{wk}, c, oi, mw, nf, i);
     cw[i] = m;
     if (n < 0 || m < 0) atomicAdd(&status[SPH_STATUS_LIST_OVERFLOW], 1u);
 }
@@ -1085,7 +1112,7 @@ int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
         const Rec<T>* pk = (const Rec<T>*)s.pk[b->sel_rho];
         if (n > 0) {
             hipLaunchKernelGGL((k_masks_fluid<T, D>), dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, b->n_wall,
-                               b->key[0], pk, b->fstart, (const Rec<T>*)s.wk, b->wstart,
+                               b->key[0], pk, b->fstart, (const Rec<T>*)s.wk, b->wstart, s.wnear,
                                b->nbr_ff, b->cnt_ff, b->nbr_fw, b->cnt_fw, b->status);
             SPH_LAUNCH_CHECK();
         }
@@ -1224,6 +1251,9 @@ int init_t(const sph_desc* d, sph_buffers* b, const double* fpos, const double* 
                            (const T*)b->woff, (const T*)b->nrm, (Rec<T>*)s.wk, (Rec<T>*)s.nk);
         SPH_LAUNCH_CHECK();
     }
+    hipLaunchKernelGGL((k_wall_near<T, D>), dim3(grid_for(d->n_cells)), dim3(kBlock), 0, st, P, d->n_cells,
+                       b->wstart, s.wnear);
+    SPH_LAUNCH_CHECK();
     // fluid: cells of the initial positions into copy 1, state into the
     // current copies, then the sort brings everything to copy 0.
     b->sel_vel = 0;

@@ -28,7 +28,8 @@ from paper_2110_02621_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-TOL32_LIGHT = 5e-4
+TOL32_LIGHT = 2e-4        # light phase, one step (measured <= 1.4e-4)
+TOL32_LIGHT_TRAJ = 5e-4   # light phase, 10 or more steps (measured <= 3.3e-4)
 
 
 @pytest.fixture(scope="module")
@@ -86,10 +87,12 @@ def test_moving_tank_trajectory(solver_mod, name, prec):
     S = solver_mod.Solver(sc, prec)
     st = O.State(O.params_from_scene(sc), sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
 
-    def tol(key):
+    def tol(key, n):
         if prec == "f64":
             return TOL64
-        return TOL32_LIGHT if key.endswith("light") else TOL32
+        if key.endswith("light"):
+            return TOL32_LIGHT if n == 1 else TOL32_LIGHT_TRAJ
+        return TOL32
 
     e0 = S.export()
     assert np.abs(e0["vel"] - st.v).max() < 1e-6  # input velocities in the fixed frame
@@ -103,7 +106,7 @@ def test_moving_tank_trajectory(solver_mod, name, prec):
         e = S.export()
         errs = errors(sc, e, st, S.export_walls()["pw"])
         print(f"  step {n}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
-        bad = {k: v for k, v in errs.items() if not v <= tol(k)}
+        bad = {k: v for k, v in errs.items() if not v <= tol(k, n)}
         assert not bad, (n, bad)
     X, V = motion(sc, done)
     assert np.abs(S.export_walls()["pos"] - (sc.wall_x + X)).max() < 1e-6 * sc.dx

@@ -9,9 +9,14 @@ largest oracle value.
 
 FP32 bound of the light phase: its density is the number density itself at
 every step (no continuity), so p = c0^2 rho0_a (sigma - sigma0)/sigma0 and a
-relative rounding error e of sigma (about 1e-6 from FP32 positions and
-sums) becomes (c0^2/(g H)) e = 200 e of the pressure scale: 5e-4 for the
-light phase's pressure and acceleration, 1e-4 (TOL32) for everything else.
+relative rounding error e of sigma becomes (c0^2/(g H)) e = 200 e of the
+pressure scale, and about H/h times that in the acceleration.  Measured on
+the oracle (tests/test_oracle_two_phase.py, test_light_phase_fp32_floor):
+the FP32 rounding of the state alone moves the air's one-step acceleration
+by ~1e-4 of its scale, one rounding of sigma by ~7e-5 more.  The light
+phase's pressure and acceleration therefore take 2e-4 after one step
+(measured on the GPU: <= 1.4e-4) and 5e-4 after 10 or more (<= 3.3e-4);
+everything else takes 1e-4 (TOL32).
 
 FP32 trajectories are compared within their predictability horizon
 (HORIZON32): on the 2-D tank the FP64 oracle started 1e-6 dx away from
@@ -32,7 +37,8 @@ from paper_2110_02621_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-TOL32_LIGHT = 5e-4
+TOL32_LIGHT = 2e-4        # light phase, one step (measured <= 1.4e-4)
+TOL32_LIGHT_TRAJ = 5e-4   # light phase, 10 or more steps (measured <= 3.3e-4)
 
 
 @pytest.fixture(scope="module")
@@ -76,10 +82,12 @@ def test_two_phase_trajectory(solver_mod, name, prec):
     S = solver_mod.Solver(sc, prec)
     P = O.params_from_scene(sc)
     st = O.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
-    def tol(key):
+    def tol(key, n):
         if prec == "f64":
             return TOL64
-        return TOL32_LIGHT if key.endswith("light") else TOL32
+        if key.endswith("light"):
+            return TOL32_LIGHT if n == 1 else TOL32_LIGHT_TRAJ
+        return TOL32
 
     done = 0
     for n in (1, 10, 100):
@@ -90,7 +98,7 @@ def test_two_phase_trajectory(solver_mod, name, prec):
         done = n
         errs = phase_errors(sc, S.export(), st, S.export_walls()["pw"])
         print(f"  step {n}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
-        bad = {k: v for k, v in errs.items() if not v <= tol(k)}
+        bad = {k: v for k, v in errs.items() if not v <= tol(k, n)}
         assert not bad, (n, bad)
     d, od = S.diag(), st.diag()
     assert d["M"] == pytest.approx(od["M"], rel=1e-12)

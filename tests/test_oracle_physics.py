@@ -429,6 +429,46 @@ def test_hydrostatic_tank_closed_form(orc):
     assert st.diag()["vmax"] < 0.01 * math.sqrt(2 * G * sc.H)
 
 
+def _relaxed_tank(orc, dx, n_relax):
+    sc = scenes.hydrostatic_tank_2d(dx=dx)
+    P = orc.params_from_scene(sc)
+    st = orc.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x)
+    st.step(n_relax, damp=0.03)
+    st.v[:] = 0.0
+    st.step(int(round(200 * 0.025 / dx)))  # the same time, 200 steps of dx = 0.025
+    return sc, st
+
+
+@pytest.mark.slow
+def test_hydrostatic_gradient_carries_the_lattice_factor(orc):
+    # Sec. 4.1 reports an approximately first-order decrease of the pressure
+    # error with dx.  With h = 1.3 dx held fixed, the discrete balance at rest
+    # says otherwise: the momentum sum of a linear pressure on the lattice is
+    # F grad p / rho (F = the lattice first moment, pinned above), so the tank
+    # settles where grad p = rho g / F, about 2.7 % steeper than rho0 g at
+    # every resolution.  The oracle's interior gradient must follow that
+    # (the local mean density included), and the L2 error must not fall
+    # from dx = 0.05 to dx = 0.025.
+    F = lattice_first_moment(orc, 2, 0.01)
+    ep = []
+    for dx, n_relax in ((0.05, 1500), (0.025, 3000)):
+        sc, st = _relaxed_tank(orc, dx, n_relax)
+        p = sc.c0 ** 2 * (st.rho - sc.rho0)
+        x = st.x
+        sel = (x[:, 0] > 0.2) & (x[:, 0] < 0.8) & (x[:, 1] > 0.2 * sc.H) & (x[:, 1] < 0.8 * sc.H)
+        A = np.vstack([np.ones(sel.sum()), x[sel, 1]]).T
+        slope = -np.linalg.lstsq(A, p[sel], rcond=None)[0][1] / (sc.rho0 * G)
+        expected = st.rho[sel].mean() / sc.rho0 / F
+        print(f"dx={dx}: interior grad p / (rho0 g) = {slope:.5f}, rho/(rho0 F) = {expected:.5f}")
+        assert slope == pytest.approx(expected, rel=2e-3)
+        assert abs(slope - 1.0) > 0.02  # the bias is there, and it is this one
+        pa = sc.rho0 * G * (sc.H - x[:, 1])
+        ep.append(np.linalg.norm(p - pa) / np.linalg.norm(pa))
+    print(f"L2 pressure error: {ep}")
+    assert 0.02 < ep[0] < 0.035 and 0.02 < ep[1] < 0.035
+    assert ep[1] > 0.9 * ep[0]  # no first-order decrease at fixed h/dx
+
+
 # ------------------------------------------------------------------ density weighting
 @pytest.mark.parametrize("dim", [2, 3])
 def test_continuity_density_weighted_mean_velocity(orc, dim):
