@@ -49,17 +49,31 @@ __device__ __forceinline__ T ref_density(const Par<T>& P, int pid) {
 }
 
 // Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8).
-// Renumber so that each XCD works on one contiguous range of particles: the
-// neighbour data a block reads then stays in that XCD's own L2.
+// C = 0: renumber so that each XCD works on one contiguous range of
+// particles, so the neighbour data a block reads stays in that XCD's own
+// L2 (the pair sweeps).  C > 0: each XCD takes chunks of C consecutive
+// blocks in turn (blocks past the last full round keep their number), which
+// keeps a chunk's neighbour rows in one L2 while spreading regions of
+// uneven work, such as the particles next to the tank floor that come first
+// in cell order, over all XCDs (the mask builders, the wall pressure and
+// the streaming kernels).
+template <int C = 0>
 __device__ __forceinline__ int logical_block() {
     const int nb = gridDim.x, b = blockIdx.x;
-    const int q = nb / kXcd, r = nb % kXcd;
     const int x = b % kXcd, k = b / kXcd;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+    if (C == 0) {
+        const int q = nb / kXcd, r = nb % kXcd;
+        return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+    }
+    const int full = nb / (C * kXcd);  // complete rounds of chunks
+    return k / C < full ? ((k / C) * kXcd + x) * C + (k % C) : b;
 }
 
+constexpr int kChunk = 64;  // blocks per chunk of the chunked numbering
+
+template <int C = 0>
 __device__ __forceinline__ int64_t global_index() {
-    return (int64_t)logical_block() * blockDim.x + threadIdx.x;
+    return (int64_t)logical_block<C>() * blockDim.x + threadIdx.x;
 }
 
 // Precision-generic math with explicit float and double forms (the float

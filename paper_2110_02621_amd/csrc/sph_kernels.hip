@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(kBlock)
                    int32_t* __restrict__ key_out, int32_t* __restrict__ pid_out,
                    T* __restrict__ off_out, T* __restrict__ vel_out, T* __restrict__ rho_out,
                    Rec<T>* __restrict__ pk_out, Rec<T>* __restrict__ vk_out) {
-    const int64_t i = global_index();
+    const int64_t i = global_index<kChunk>();
     if (i >= n) return;
     const int64_t s = perm[i];
     key_out[i] = key_in[s];
@@ -332,7 +332,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
     k_normals(Par<T> P, int64_t nw, const int32_t* __restrict__ wkey, const T* __restrict__ woff,
               const int32_t* __restrict__ wstart, T* __restrict__ nrm) {
-    const int64_t w = global_index();
+    const int64_t w = global_index<kChunk>();
     if (w >= nw) return;
     const T* o0 = woff;
     const T* o1 = woff + nw;
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(kBlock)
               int32_t* __restrict__ pid_out, T* __restrict__ off_out, T* __restrict__ sigma_out,
               const T* __restrict__ sigma_in, Rec<T>* __restrict__ pk, Rec<T>* __restrict__ vk,
               uint32_t* __restrict__ status) {
-    const int64_t i = global_index();
+    const int64_t i = global_index<kChunk>();
     if (i >= nf) return;
     const T* o0 = off;
     const T* o1 = off + nf;
@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(kBlock)
     k_wall_bc(Par<T> P, NbrMask LWF, int64_t nf, int64_t nw, const int32_t* __restrict__ wkey,
               const int32_t* __restrict__ fstart, const Rec<T>* __restrict__ pk,
               const Rec<T>* __restrict__ vk, Rec<T>* __restrict__ wk, T* __restrict__ pw) {
-    const int64_t w = global_index();
+    const int64_t w = global_index<kChunk>();
     if (w >= nw) return;
     if (nf == 0 || (LWF.mask && LWF.count[w] == 0)) {  // no fluid neighbour: Eq. (12) gives 0
         pw[w] = T(0);
@@ -840,7 +840,7 @@ __global__ void __launch_bounds__(kBlock)
                   const uint8_t* __restrict__ wnear, uint64_t* __restrict__ mf, int32_t* __restrict__ cf,
                   uint64_t* __restrict__ mw, int32_t* __restrict__ cw, uint32_t* __restrict__ status) {
     __shared__ Rec<T> stage_p[kBlock / 64][kStageM];
-    const int64_t i0 = global_index();
+    const int64_t i0 = global_index<kChunk>();
     const int64_t ib = i0 - (threadIdx.x & 63);
     if (ib >= nf) return;  // the whole wave is past the end
     const bool act = i0 < nf;
@@ -875,7 +875,7 @@ __global__ void __launch_bounds__(kBlock)
                  const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ pk,
                  const int32_t* __restrict__ fstart, uint64_t* __restrict__ m,
                  int32_t* __restrict__ cnt, uint32_t* __restrict__ status) {
-    const int64_t w = global_index();
+    const int64_t w = global_index<kChunk>();
     if (w >= nw) return;
     int c[3];
     cell_of(P, wkey[w], c);
