@@ -805,6 +805,58 @@ __device__ __forceinline__ void visit4(const Par<T>& P, const NbrMask& M, int64_
     walk_src<T, D>(P, start, src, c, oi, f);
 }
 
+// The wall neighbours of fluid query i from its masks, for the pair sweeps:
+// the same rows and ascending order as mask_src (so the same sums), with
+// the wall's position record (wk) and, when nk is given, its normal record
+// loaded one pair ahead, so each pair's gathers are in flight while the
+// pair before it is computed.  f(w, d, r2, q, n) gets both records (n = 0
+// without nk).  Queries whose masks overflowed walk the cells.
+template <typename T, int D, typename F>
+__device__ __forceinline__ void visit_walls(const Par<T>& P, const NbrMask& M, int64_t i,
+                                            const int32_t* __restrict__ start, const Rec<T>* __restrict__ wk,
+                                            const Rec<T>* __restrict__ nk, const int c[3], const T oi[3], F&& f) {
+    auto nrm = [&](int j) { return nk ? ld4(nk, j) : Rec<T>{T(0), T(0), T(0), T(0)}; };
+    if (!M.mask || M.count[i] < 0) {
+        walk_src<T, D>(P, start, PackSrc<T>{wk}, c, oi,
+                       [&](int j, const T* d, T r2, uint32_t, const Rec<T>& q) { f(j, d, r2, q, nrm(j)); });
+        return;
+    }
+    for_rows<T, D>(P, start, c, oi, [&](const Row& R, T sy, T sz) {
+        // cur: the bits still to visit of the current word (candidates
+        // wb + bit), later: the row's second word
+        uint64_t cur = M.mask[(int64_t)(R.r * kMaskWords + 0) * M.n + i];
+        uint64_t later = R.j1 - R.base > 64 ? M.mask[(int64_t)(R.r * kMaskWords + 1) * M.n + i] : 0ull;
+        int wb = R.base;
+        if (cur == 0) {
+            cur = later;
+            later = 0;
+            wb += 64;
+        }
+        if (cur == 0) return;
+        int j = wb + __builtin_ctzll(cur);
+        cur &= cur - 1;
+        Rec<T> q = ld4(wk, j), n = nrm(j);
+        while (true) {
+            if (cur == 0 && later != 0) {
+                cur = later;
+                later = 0;
+                wb += 64;
+            }
+            const bool more = cur != 0;
+            const int jn = more ? wb + __builtin_ctzll(cur) : j;
+            cur &= cur - 1;
+            const Rec<T> qn = ld4(wk, jn), nn = nrm(jn);  // the next pair's records (this one's when last)
+            T d[3];
+            const T r2 = rel2<T, D>(oi, q.x, q.y, q.z, row_shift(j, R.jm, R.jp, P.L), sy, sz, d);
+            f(j, d, r2, q, n);
+            if (!more) break;
+            j = jn;
+            q = qn;
+            n = nn;
+        }
+    });
+}
+
 template <typename T, int D, typename F>
 __device__ __forceinline__ void visit(const Par<T>& P, const NbrMask& M, int64_t i,
                                       const int32_t* __restrict__ start, const T* __restrict__ o0,

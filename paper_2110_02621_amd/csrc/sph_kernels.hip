@@ -659,8 +659,8 @@ __global__ void __launch_bounds__(kBlock)
                                fluid_g);
     if (!act) return;
     if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
-        visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
-                     [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+        visit_walls<T, D>(P, LW, i, wstart, wk, nullptr, c, oi,
+                     [&](int, const T d[3], T r2, const Rec<T>& q, const Rec<T>&) {
                          const T r = MP ? pair_r(r2) : root(r2);
                          const KernelWF<T> k = wendland_WF(P, r);
                          if (MP) kahan_add(sig, comp, k.W);
@@ -776,8 +776,8 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
                               fluid_g);
     if (!act) return;
     if (nw > 0 && (!LW.mask || LW.count[i] != 0))  // no wall neighbour: nothing to add
-        visit4<T, D>(P, LW, i, wstart, PackSrc<T>{wk}, c, oi,
-                     [&](int w, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+        visit_walls<T, D>(P, LW, i, wstart, wk, (P.penalty || light) ? nk : nullptr, c, oi,
+                     [&](int, const T d[3], T r2, const Rec<T>& q, const Rec<T>& nw4) {
                          const T r = pair_r(r2);
                          const KernelWF<T> k = wendland_WF(P, r);
                          kahan_add(s, comp, k.W);
@@ -794,7 +794,6 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
                          T pen = T(0);
                          T nv[3] = {0, 0, 0};
                          if (P.penalty || light) {
-                             const Rec<T> nw4 = ld4(nk, w);
                              nv[0] = nw4.x;
                              nv[1] = nw4.y;
                              nv[2] = D == 3 ? nw4.z : T(0);
