@@ -118,6 +118,12 @@ typedef struct sph_desc {
     double motion_amp[3]; /* prescribed rigid translation of every wall dummy (the tank),   */
     double motion_freq;   /* X(t) = motion_amp sin(2 pi motion_freq t) at t = nstep dt      */
                           /* (Sec. 4.4); 0 = fixed walls.  See "Moving tank" below.        */
+    int32_t cross_phase;  /* two phases, momentum of a light particle with a heavy neighbour:
+                             1 = the light phase sees the heavy particle as a moving wall
+                             dummy (Secs. 2.1, 2.5): p* of Eq. (11) with p_w = p_j, density
+                             rho0_light + p_j/c0^2, mass rho0_light dx^d; 0 = p* of Eq. (8)
+                             with each side's own state.  0 or 1. */
+    int32_t reserved1;
     /* derived by sph_configure: */
     double cell;         /* cell edge L_c = 2h, rounded to T */
     double sigma0;       /* reference number density of Eq. (17): full lattice sum */

@@ -32,7 +32,7 @@ class OrcParams(C.Structure):
         ("a_wall", C.c_double * 3),
         ("sigma0", C.c_double),
         ("two_phase", C.c_int32),
-        ("reserved", C.c_int32),
+        ("cross_phase", C.c_int32),
         ("n_heavy", C.c_int64),
         ("rho0_light", C.c_double),
         ("wall_v", C.c_double * 3),
@@ -110,7 +110,7 @@ def _check(rc, what):
 def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
            a_wall=(0.0, 0.0, 0.0), sigma0=None, penalty_on=True, n_heavy=None,
            rho0_light=None, wall_v=(0.0, 0.0, 0.0), motion_amp=(0.0, 0.0, 0.0),
-           motion_freq=0.0) -> OrcParams:
+           motion_freq=0.0, cross_phase=0) -> OrcParams:
     """Parameter block.  sigma0 defaults to the lattice sum of Eq. (17).
     Two phases: fluid particles with index >= n_heavy have reference density
     rho0_light (both given, or neither for a single phase).  wall_v is the
@@ -126,6 +126,7 @@ def params(dim, dx, h, rho0, c, mu=0.0, gamma_p=1.0, dt=0.0, g=(0.0, 0.0, 0.0),
         p.a_wall[k] = float(a_wall[k]) if k < len(a_wall) else 0.0
     p.sigma0 = sigma0_lattice(dim, dx, h) if sigma0 is None else float(sigma0)
     p.two_phase = 1 if rho0_light is not None else 0
+    p.cross_phase = int(cross_phase)
     p.n_heavy = int(n_heavy) if n_heavy is not None else 0
     p.rho0_light = float(rho0_light) if rho0_light is not None else float(rho0)
     for k in range(3):
@@ -139,7 +140,7 @@ def params_from_scene(sc, **over) -> OrcParams:
     kw = dict(dim=sc.dim, dx=sc.dx, h=sc.h, rho0=sc.rho0, c=sc.c0, mu=sc.mu,
               gamma_p=sc.gamma_p, dt=sc.dt, g=tuple(sc.g), penalty_on=sc.penalty_all)
     if getattr(sc, "rho0_light", None) is not None:
-        kw.update(n_heavy=sc.n_heavy, rho0_light=sc.rho0_light)
+        kw.update(n_heavy=sc.n_heavy, rho0_light=sc.rho0_light, cross_phase=getattr(sc, "cross_phase", 0))
     if getattr(sc, "motion_freq", 0.0):
         kw.update(motion_amp=tuple(sc.motion_amp), motion_freq=sc.motion_freq)
     kw.update(over)

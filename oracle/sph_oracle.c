@@ -97,7 +97,12 @@ typedef struct {
     double a_wall[3];   /* wall acceleration in Eq. (12) */
     double sigma0;      /* reference number density of Eq. (17) */
     int32_t two_phase;  /* 1: particles with index >= n_heavy are the light phase */
-    int32_t reserved;
+    int32_t cross_phase; /* two phases, momentum of a light particle i with a heavy
+                            neighbour j: 0 = the printed Riemann p* of Eq. (8) with each
+                            side's own state; 1 = the light phase sees the heavy particle
+                            as a moving wall dummy: p* of Eq. (11) with p_w = p_j, the
+                            light phase's EOS density rho0_light + p_j/c^2 and mass
+                            rho0_light dx^d (Secs. 2.1, 2.5) */
     int64_t n_heavy;    /* number of heavy-phase fluid particles (indices first) */
     double rho0_light;  /* reference density of the light phase */
     double wall_v[3];   /* velocity of the wall dummies in the pair terms (orc_step sets
@@ -736,12 +741,19 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                     double rho_j, pstar, m;
                     if (set == 0) {
                         for (int k = 0; k < dim; ++k) vj[k] = fv[j * dim + k];
-                        rho_j = frho[j];
-                        double p_j = eos_p(P, j, rho_j);
-                        riemann_out rs =
-                            riemann(rho_i, dot(dim, vi, e), p_i, rho_j, dot(dim, vj, e), p_j, P->c);
-                        pstar = rs.pstar;
-                        m = mass_of(P, j);
+                        double p_j = eos_p(P, j, frho[j]);
+                        if (P->cross_phase && is_light(P, i) && !is_light(P, j)) {
+                            /* the heavy particle as a moving dummy of the light phase */
+                            rho_j = eos_rho(P, i, p_j);
+                            pstar = (rho_i * p_j + rho_j * p_i) / (rho_i + rho_j); /* Eq. (11) */
+                            m = mass_of(P, i);
+                        } else {
+                            rho_j = frho[j];
+                            riemann_out rs =
+                                riemann(rho_i, dot(dim, vi, e), p_i, rho_j, dot(dim, vj, e), p_j, P->c);
+                            pstar = rs.pstar;
+                            m = mass_of(P, j);
+                        }
                     } else {
                         for (int k = 0; k < dim; ++k) vj[k] = P->wall_v[k];
                         double p_w = pw[j];

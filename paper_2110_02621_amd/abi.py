@@ -37,6 +37,7 @@ class Desc(C.Structure):
         ("g", C.c_double * 3), ("a_wall", C.c_double * 3), ("lo", C.c_double * 3),
         ("hi", C.c_double * 3), ("n_heavy", C.c_int64), ("rho0_light", C.c_double),
         ("motion_amp", C.c_double * 3), ("motion_freq", C.c_double),
+        ("cross_phase", C.c_int32), ("reserved1", C.c_int32),
         ("cell", C.c_double), ("sigma0", C.c_double), ("grid", C.c_int32 * 3),
         ("reserved2", C.c_int32), ("n_cells", C.c_int64),
     ]

@@ -40,6 +40,7 @@ struct Par {
     T rho0L;         // light-phase reference density
     T rho0L_over_sigma0;
     T fk[3];         // uniform velocity added by this call's kick (moving tank; else 0)
+    int cross_phase; // two phases: light particles see heavy ones as moving wall dummies
 };
 
 // Reference density of the particle with initial index pid.

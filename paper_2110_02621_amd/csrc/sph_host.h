@@ -92,6 +92,7 @@ inline Par<T> make_par(const sph_desc* d) {
     P.psi_min = T(1e-4 / h);
     P.two_phase = d->two_phase ? 1 : 0;
     P.n_heavy = d->two_phase ? (int)d->n_heavy : 0;
+    P.cross_phase = d->two_phase ? d->cross_phase : 0;
     P.rho0L = T(d->two_phase ? d->rho0_light : d->rho0);
     P.rho0L_over_sigma0 = T((d->two_phase ? d->rho0_light : d->rho0) / d->sigma0);
     return P;

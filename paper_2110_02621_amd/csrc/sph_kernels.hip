@@ -743,9 +743,17 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
         kahan_add(s, comp, k.W);
         const T F = k.F;
         const T drj = q.w;
-        const T r0j = MP ? vj.w : P.rho0;
-        const T rho_j = r0j + drj;
+        T r0j = MP ? vj.w : P.rho0;
         const T p_j = P.c2 * drj;
+        // two phases with cross_phase: a light particle sees a heavy neighbour
+        // as a moving wall dummy (p* of Eq. (11), the light phase's EOS
+        // density and mass); otherwise each side keeps its own state
+        const bool dummy = MP && P.cross_phase && light && r0j != r0i;
+        T rho_j = r0j + drj;
+        if (dummy) {
+            r0j = r0i;
+            rho_j = r0i + p_j * P.inv_c2;
+        }
         const T vjk[3] = {vj.x, vj.y, vj.z};
         T dv[3];
         T vd = T(0);
@@ -755,7 +763,7 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
             vd += dv[k] * d[k];
         }
         const T jump = -vd * rinv;  // U_L - U_R
-        const T beta = minv(T(3) * maxv(jump, T(0)), P.c);
+        const T beta = dummy ? T(0) : minv(T(3) * maxv(jump, T(0)), P.c);
         const T sum = rho_i + rho_j;
         const T qq = rcp(rho_j * sum);  // 1/(rho_j (rho_i + rho_j))
         const T pstar = (rho_i * p_j + rho_j * p_i + rho_i * rho_j * beta * jump) * (rho_j * qq);
@@ -1486,6 +1494,7 @@ int sph_configure(sph_desc* d) {
     if (!(d->h > 0.0) || !(d->dx > 0.0) || !(d->c0 > 0.0) || !(d->rho0 > 0.0) || !(d->dt > 0.0))
         return SPH_ERR_CONFIG;
     if (d->two_phase != 0 && d->two_phase != 1) return SPH_ERR_CONFIG;
+    if (d->cross_phase != 0 && d->cross_phase != 1) return SPH_ERR_CONFIG;
     if (d->two_phase && (!(d->rho0_light > 0.0) || d->n_heavy < 0 || d->n_heavy > (int64_t)INT32_MAX))
         return SPH_ERR_CONFIG;
     if (!std::isfinite(d->motion_freq) || d->motion_freq < 0.0) return SPH_ERR_CONFIG;

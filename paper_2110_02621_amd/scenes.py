@@ -58,6 +58,10 @@ class Scene:
     # X(t) = motion_amp sin(2 pi motion_freq t)
     motion_amp: tuple = (0.0, 0.0, 0.0)
     motion_freq: float = 0.0
+    # two phases: 1 = a light particle sees a heavy neighbour as a moving wall
+    # dummy (p* of Eq. (11), the light phase's EOS density and mass); 0 = the
+    # Riemann p* of Eq. (8) with each side's own state
+    cross_phase: int = 0
 
     @property
     def n_fluid(self) -> int:

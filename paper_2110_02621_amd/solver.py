@@ -36,6 +36,7 @@ def make_desc(scene, precision="f32") -> abi.Desc:
         d.two_phase = 1
         d.n_heavy = int(scene.n_heavy)
         d.rho0_light = float(scene.rho0_light)
+        d.cross_phase = int(getattr(scene, "cross_phase", 0))
     d.motion_freq = float(getattr(scene, "motion_freq", 0.0))
     for k in range(3):
         d.motion_amp[k] = float(scene.motion_amp[k]) if d.motion_freq else 0.0

@@ -302,18 +302,21 @@ def _fp32_state(sc, x, v, rho):
             r0 + (rho - r0).astype(np.float32).astype(np.float64))
 
 
-def test_light_phase_fp32_floor(orc):
+@pytest.mark.parametrize("cross_phase", [0, 1])
+def test_light_phase_fp32_floor(orc, cross_phase):
     # How far the FP64 oracle's own light-phase (air) results move under
     # the roundings any FP32 evaluation of the step makes, on the 2-D
     # two-phase tank after 10 steps.  The air's density is the number
     # density itself, rho = rho0_a sigma / sigma0, so one rounding of sigma
-    # (relative 6e-8) reaches its pressure amplified by c0^2/(gH) = 200 and
-    # its acceleration by a further ~H/h: both roundings below move the
-    # air's acceleration by several 1e-5 of its scale, and together by
-    # about 1e-4, while the water moves by ~1e-5 or less.  This is the floor
-    # under the FP32 GPU path's one-step light-phase error (~1.4e-4
-    # measured), and why its bar there is 2e-4 rather than 1e-4.
-    sc = scenes.two_phase_tank_2d(dx=0.04, steps=100)
+    # (relative 6e-8) reaches its pressure amplified by c0^2/(gH) = 200.
+    # With the printed Riemann p* across the interface (cross_phase = 0) the
+    # air next to water takes p* ~ its own pressure, and both roundings
+    # below move its acceleration by several 1e-5 of its scale, together
+    # about 1e-4 (the water ~1e-5 or less): the floor under the FP32 path's
+    # one-step light-phase error in that reading (the default).  With the
+    # water seen as moving wall dummies (cross_phase = 1) the same roundings
+    # move the air's acceleration by ~1e-6.
+    sc = scenes.two_phase_tank_2d(dx=0.04, steps=100).with_params(cross_phase=cross_phase)
     P = orc.params_from_scene(sc)
     st = orc.State(P, sc.fluid_x, sc.fluid_v, sc.fluid_rho, sc.wall_x).step(10)
     heavy = np.arange(sc.n_fluid) < sc.n_heavy
@@ -336,6 +339,43 @@ def test_light_phase_fp32_floor(orc):
     e_sigma = a_err(a32, a64, light)
     print(f"air acceleration: state rounding {e_state[0]:.2e}, sigma rounding {e_sigma:.2e}; "
           f"water: {e_state[1]:.2e}")
-    assert 3e-5 < e_state[0] < 2e-4 and 3e-5 < e_sigma < 2e-4
-    assert e_state[0] + e_sigma > 1e-4
+    if cross_phase == 0:
+        assert 3e-5 < e_state[0] < 2e-4 and 3e-5 < e_sigma < 2e-4
+        assert e_state[0] + e_sigma > 1e-4
+    else:
+        assert e_state[0] < 1e-5 and e_sigma < 1e-5
     assert e_state[1] < 5e-5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_light_phase_sees_heavy_particles_as_wall_dummies(orc, dim):
+    # cross_phase = 1 (Secs. 2.1, 2.5: the light phase experiences the heavy
+    # phase like a moving wall): an air particle's acceleration next to
+    # water particles equals its acceleration next to wall dummies at the
+    # same places carrying the water's pressures (Eq. (11), the air's EOS
+    # density and mass for the dummy), with viscosity and the wall penalty
+    # off; the water's own accelerations do not change.
+    rng = np.random.default_rng(31)
+    dx, c = 0.01, 30.0
+    n = 10 if dim == 2 else 6
+    pts = lattice(dim, n, dx) + rng.normal(0, 0.05 * dx, (n ** dim, dim))
+    low = pts[:, -1] < 0.5 * n * dx
+    xh, xl = pts[low], pts[~low]
+    nh = len(xh)
+    v = rng.normal(0, 0.2, (len(pts), dim))
+    vh, vl = v[:nh], v[nh:]
+    ph = rng.uniform(0.0, 400.0, nh)           # water pressures
+    pl = rng.uniform(0.0, 1.0, len(xl))        # air pressures
+    rho_h, rho_l = RHO_W + ph / c ** 2, RHO_A + pl / c ** 2
+    kw = dict(dim=dim, dx=dx, h=1.3 * dx, rho0=RHO_W, c=c, dt=1e-4, gamma_p=0.0, penalty_on=False)
+    Pd = orc.params(n_heavy=nh, rho0_light=RHO_A, cross_phase=1, **kw)
+    A = orc.momentum(Pd, np.concatenate([xh, xl]), np.concatenate([vh, vl]), np.concatenate([rho_h, rho_l]),
+                     np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    Pw = orc.params(n_heavy=0, rho0_light=RHO_A, **kw)  # every fluid particle light, water as walls
+    Aw = orc.momentum(Pw, xl, vl, rho_l, xh, ph, np.zeros((nh, dim)))
+    assert np.abs(A[nh:] - Aw).max() < 1e-12 * np.abs(Aw).max()
+    P0 = orc.params(n_heavy=nh, rho0_light=RHO_A, cross_phase=0, **kw)
+    A0 = orc.momentum(P0, np.concatenate([xh, xl]), np.concatenate([vh, vl]), np.concatenate([rho_h, rho_l]),
+                      np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    assert np.array_equal(A0[:nh], A[:nh])
+    assert np.abs(A0[nh:] - A[nh:]).max() > 1e-3 * np.abs(A[nh:]).max()  # the reading matters for the air
