@@ -417,6 +417,9 @@ def main():
         # differences to ~3e-5 at this size, the FP32 one to ~1e-3)
         adj["f64"] = adjoint_timing(scenes, args, "f64")
         adj["f64"].pop("workload")
+        adj["ratio_note"] = ("ratio: FP32 forward and its FP64-accumulated backward (incl. recompute) over that "
+                             "forward; f64.ratio: the FP64 adjoint over its own forward; adjoint_fwd_ratio: the "
+                             "FP64 adjoint's backward over the FP32 forward")
         print(f"[bench] adjoint f64 fwd {adj['f64']['t_forward_s']:.3f} s bwd {adj['f64']['t_backward_s']:.3f} s",
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
@@ -484,7 +487,9 @@ def main():
         "fp32_wedge": wedge,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
-        "adjoint_fwd_ratio": adj["ratio"] if adj else None,
+        # the gradient that meets 1e-3 on every component (FP64 forward and
+        # backward) against the production FP32 forward of the same run
+        "adjoint_fwd_ratio": (adj["f64"]["t_backward_s"] / adj["t_forward_s"]) if adj else None,
         "adjoint": adj,
         "roofline": roofline,
         "roofline_frac_unpacked_fp32": round(ach / PEAK_FP32_UNPACKED, 4),
