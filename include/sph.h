@@ -119,10 +119,13 @@ typedef struct sph_desc {
     double motion_freq;   /* X(t) = motion_amp sin(2 pi motion_freq t) at t = nstep dt      */
                           /* (Sec. 4.4); 0 = fixed walls.  See "Moving tank" below.        */
     int32_t cross_phase;  /* two phases, momentum of a light particle with a heavy neighbour:
-                             1 = the light phase sees the heavy particle as a moving wall
-                             dummy (Secs. 2.1, 2.5): p* of Eq. (11) with p_w = p_j, density
-                             rho0_light + p_j/c0^2, mass rho0_light dx^d; 0 = p* of Eq. (8)
-                             with each side's own state.  0 or 1. */
+                             0 = p* of Eq. (8) with each side's own state; 1 = the light
+                             phase sees the heavy particle as a moving wall dummy (Secs. 2.1,
+                             2.5): p* of Eq. (11) with p_w = p_j, density rho0_light +
+                             p_w/c0^2, mass rho0_light dx^d; 2 = the same with p_w the
+                             pressure extrapolated to the heavy particle from its light
+                             neighbours by Eq. (12) divided by rho_f, with the tank's
+                             acceleration (computed at the start of sph_forces(MOMENTUM)). */
     int32_t reserved1;
     /* derived by sph_configure: */
     double cell;         /* cell edge L_c = 2h, rounded to T */

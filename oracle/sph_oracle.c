@@ -101,8 +101,10 @@ typedef struct {
                             neighbour j: 0 = the printed Riemann p* of Eq. (8) with each
                             side's own state; 1 = the light phase sees the heavy particle
                             as a moving wall dummy: p* of Eq. (11) with p_w = p_j, the
-                            light phase's EOS density rho0_light + p_j/c^2 and mass
-                            rho0_light dx^d (Secs. 2.1, 2.5) */
+                            light phase's EOS density rho0_light + p_w/c^2 and mass
+                            rho0_light dx^d (Secs. 2.1, 2.5); 2 = the same with p_w the
+                            pressure extrapolated to j from its light neighbours by the
+                            two-phase form of Eq. (12), a_w = the tank's acceleration */
     int64_t n_heavy;    /* number of heavy-phase fluid particles (indices first) */
     double rho0_light;  /* reference density of the light phase */
     double wall_v[3];   /* velocity of the wall dummies in the pair terms (orc_step sets
@@ -703,6 +705,50 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
         return rc;
     }
     int err = 0;
+    /* cross_phase = 2: the pressure each heavy particle carries as a moving
+     * wall dummy of the light phase, from its light neighbours by the
+     * two-phase form of Eq. (12) (each term divided by rho_f), with the
+     * tank's acceleration as the dummy's; 0 without light neighbours. */
+    double *pd = NULL;
+    if (P->two_phase && P->cross_phase == 2) {
+        pd = (double *)calloc((size_t)(nf ? nf : 1), sizeof(double));
+        if (!pd) err = ORC_ERR_ALLOC;
+    }
+    if (pd) {
+#pragma omp parallel
+        {
+            int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < nf; ++j) {
+                if (is_light(P, j)) continue;
+                const double *xj = fx + j * dim;
+                int cnt = cs_query(&sf, xj, rc2, nbr, ORC_NBR_CAP);
+                if (cnt < 0) {
+                    err = ORC_ERR_NBR_CAP;
+                    cnt = 0;
+                }
+                double sW = 0.0, sP = 0.0, sR[3] = {0, 0, 0};
+                for (int a = 0; a < cnt; ++a) {
+                    int64_t l = nbr[a];
+                    if (!is_light(P, l)) continue;
+                    double r2 = 0.0, rjl[3] = {0, 0, 0};
+                    for (int k = 0; k < dim; ++k) {
+                        rjl[k] = xj[k] - fx[l * dim + k];
+                        r2 += rjl[k] * rjl[k];
+                    }
+                    double W = orc_W(dim, h, sqrt(r2));
+                    double rl = frho[l];
+                    sW += W / rl;
+                    sP += eos_p(P, l, rl) / rl * W;
+                    for (int k = 0; k < dim; ++k) sR[k] += rjl[k] * W;
+                }
+                double gR = 0.0;
+                for (int k = 0; k < dim; ++k) gR += (P->g[k] - P->a_wall[k]) * sR[k];
+                pd[j] = sW > 0.0 ? (sP + gR) / sW : 0.0;
+            }
+            free(nbr);
+        }
+    }
 #pragma omp parallel
     {
         int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * ORC_NBR_CAP);
@@ -743,7 +789,10 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
                         for (int k = 0; k < dim; ++k) vj[k] = fv[j * dim + k];
                         double p_j = eos_p(P, j, frho[j]);
                         if (P->cross_phase && is_light(P, i) && !is_light(P, j)) {
-                            /* the heavy particle as a moving dummy of the light phase */
+                            /* the heavy particle as a moving dummy of the light phase,
+                             * carrying its own pressure (1) or the one extrapolated
+                             * from its light neighbours (2) */
+                            if (pd) p_j = pd[j];
                             rho_j = eos_rho(P, i, p_j);
                             pstar = (rho_i * p_j + rho_j * p_i) / (rho_i + rho_j); /* Eq. (11) */
                             m = mass_of(P, i);
@@ -782,6 +831,7 @@ int orc_momentum(const orc_params *P, int64_t nf, const double *fx, const double
         }
         free(nbr);
     }
+    free(pd);
     cs_free(&sf);
     cs_free(&sw);
     return err;

@@ -153,6 +153,7 @@ struct Scratch {
     void* wk;
     void* nk;
     uint8_t* wnear;  // n_cells: 1 when a wall particle lies in the cell's neighbour cells (set by sph_init)
+    void* pd;        // n_fluid T: two phases, cross_phase 2: each heavy particle's dummy pressure
     size_t bytes;
 };
 
@@ -183,6 +184,7 @@ inline Scratch layout(const sph_desc* d, int64_t nf, int64_t nw, void* base) {
     s.wk = take(4 * ts * (size_t)nw);
     s.nk = take(4 * ts * (size_t)nw);
     s.wnear = (uint8_t*)take((size_t)d->n_cells);
+    s.pd = take(d->two_phase && d->cross_phase == 2 ? ts * (size_t)nf : 0);
     s.bytes = o;
     return s;
 }

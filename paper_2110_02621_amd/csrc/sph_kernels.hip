@@ -682,6 +682,46 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
+// Two phases, cross_phase 2: the pressure each heavy particle carries as a
+// moving wall dummy of the light phase, extrapolated from its light
+// neighbours by the two-phase form of Eq. (12) (each term divided by rho_f),
+// with g - a_w of the tank; 0 for light particles and for heavy ones
+// without light neighbours.
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+    k_dummy_pressure(Par<T> P, NbrMask LF, int64_t nf, const int32_t* __restrict__ key,
+                     const int32_t* __restrict__ pid, const int32_t* __restrict__ fstart,
+                     const Rec<T>* __restrict__ pk, const Rec<T>* __restrict__ vk, T* __restrict__ pd) {
+    const int64_t i = global_index<kChunk>();
+    if (i >= nf) return;
+    if (pid[i] >= P.n_heavy) {
+        pd[i] = T(0);
+        return;
+    }
+    int c[3];
+    cell_of(P, key[i], c);
+    const Rec<T> me = pk[i];
+    const T oi[3] = {me.x, me.y, me.z};
+    T sW = T(0), sP = T(0), sR[3] = {0, 0, 0};
+    visit4<T, D>(P, LF, i, fstart, PackSrc<T>{pk}, c, oi, [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q) {
+        const T r0j = ld4(vk, j).w;
+        if (r0j == P.rho0) return;  // a heavy neighbour
+        const T W = wendland_W(P, pair_r(r2));
+        const T rinv = T(1) / (r0j + q.w);
+        sW += W * rinv;
+        sP += P.c2 * q.w * W * rinv;
+#pragma unroll
+        for (int k = 0; k < D; ++k) sR[k] += W * d[k];
+    });
+    T gR = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) gR += P.gw[k] * sR[k];
+    pd[i] = sW > T(0) ? (sP + gR) / sW : T(0);
+}
+
+// ---------------------------------------------------------------------------
 // Momentum, Eq. (10) with p* of Eq. (8) (fluid) and Eq. (11) (walls),
 // viscous term, penalty force Eqs. (13)-(15), gravity, second kick Eq. (22).
 // Per fluid pair, with U_L - U_R = -(v_ij . r_ij)/r and F = W'(r)/r:
@@ -702,7 +742,7 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
                const Rec<T>* __restrict__ vk, const int32_t* __restrict__ wstart,
                const Rec<T>* __restrict__ wk, const Rec<T>* __restrict__ nk, T* __restrict__ acc,
                T* __restrict__ vel_out, Rec<T>* __restrict__ vk_out, T* __restrict__ sigma_next,
-               int kick) {
+               const T* __restrict__ pd, int kick) {
     __shared__ Rec<T> stage[2 * kWaves * kStage];
     __shared__ int perm[kBlock];
     __shared__ int hist[16];
@@ -732,7 +772,7 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
     // sigma of these positions, the next density update's sum (Eq. (4)):
     // every visited pair, self included, fluid then walls, as k_density sums it
     T s = T(0), comp = T(0);
-    auto fluid = [&](int, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
+    auto fluid = [&](int j, const T d[3], T r2, uint32_t, const Rec<T>& q, const Rec<T>& vj) {
         // no branch for r = 0 (the particle itself, or a coincident one): with
         // the reciprocal root taken of 1 there, every part of its force carries
         // r or d and adds an exact zero, and the velocity record is read
@@ -744,13 +784,16 @@ __global__ void __launch_bounds__(kBlock, kMomentumWaves<T>)
         const T F = k.F;
         const T drj = q.w;
         T r0j = MP ? vj.w : P.rho0;
-        const T p_j = P.c2 * drj;
+        T p_j = P.c2 * drj;
         // two phases with cross_phase: a light particle sees a heavy neighbour
         // as a moving wall dummy (p* of Eq. (11), the light phase's EOS
-        // density and mass); otherwise each side keeps its own state
+        // density and mass), carrying the heavy particle's own pressure (1)
+        // or the one extrapolated from its light neighbours (2); otherwise
+        // each side keeps its own state
         const bool dummy = MP && P.cross_phase && light && r0j != r0i;
         T rho_j = r0j + drj;
         if (dummy) {
+            if (P.cross_phase == 2) p_j = ldg(pd, j);
             r0j = r0i;
             rho_j = r0i + p_j * P.inv_c2;
         }
@@ -1211,13 +1254,23 @@ int forces_t(const sph_desc* d, sph_buffers* b, unsigned which, hipStream_t st) 
         b->sel_rho = 1 - sr;
     } else {
         const int kick = (which & SPH_NO_KICK) ? 0 : 1;
+        const bool dummies = d->two_phase && d->cross_phase == 2;
+        if (nf > 0 && dummies) {  // the heavy particles' dummy pressures, g - a_w of the tank at nstep
+            Par<T> Q = P;
+            const Motion m = motion_at(d, b->nstep);
+            for (int k = 0; k < 3; ++k) Q.gw[k] = T(d->g[k] - d->a_wall[k] - (moving(d) ? m.A[k] : 0.0));
+            hipLaunchKernelGGL((k_dummy_pressure<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, st, Q, mask_ff(b),
+                               nf, b->key[0], b->pid[0], b->fstart, (const Rec<T>*)s.pk[sr],
+                               (const Rec<T>*)s.vk[sv], (T*)s.pd);
+            SPH_LAUNCH_CHECK();
+        }
         if (nf > 0) {
             auto kern = d->two_phase ? k_momentum<T, D, true> : k_momentum<T, D, false>;
             hipLaunchKernelGGL(kern, dim3(grid_for(nf)), dim3(kBlock), 0, st, P,
                                mask_ff(b), mask_fw(b), nf, nw, b->key[0], b->pid[0], b->fstart,
                                (const Rec<T>*)s.pk[sr], (const Rec<T>*)s.vk[sv], b->wstart, wk,
                                (const Rec<T>*)s.nk, (T*)b->acc, (T*)b->vel[1 - sv],
-                               (Rec<T>*)s.vk[1 - sv], (T*)s.sig, kick);
+                               (Rec<T>*)s.vk[1 - sv], (T*)s.sig, dummies ? (const T*)s.pd : nullptr, kick);
             SPH_LAUNCH_CHECK();
         }
         if (kick) b->sel_vel = 1 - sv;
@@ -1494,7 +1547,7 @@ int sph_configure(sph_desc* d) {
     if (!(d->h > 0.0) || !(d->dx > 0.0) || !(d->c0 > 0.0) || !(d->rho0 > 0.0) || !(d->dt > 0.0))
         return SPH_ERR_CONFIG;
     if (d->two_phase != 0 && d->two_phase != 1) return SPH_ERR_CONFIG;
-    if (d->cross_phase != 0 && d->cross_phase != 1) return SPH_ERR_CONFIG;
+    if (d->cross_phase < 0 || d->cross_phase > 2) return SPH_ERR_CONFIG;
     if (d->two_phase && (!(d->rho0_light > 0.0) || d->n_heavy < 0 || d->n_heavy > (int64_t)INT32_MAX))
         return SPH_ERR_CONFIG;
     if (!std::isfinite(d->motion_freq) || d->motion_freq < 0.0) return SPH_ERR_CONFIG;

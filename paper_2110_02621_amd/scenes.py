@@ -59,8 +59,10 @@ class Scene:
     motion_amp: tuple = (0.0, 0.0, 0.0)
     motion_freq: float = 0.0
     # two phases: 1 = a light particle sees a heavy neighbour as a moving wall
-    # dummy (p* of Eq. (11), the light phase's EOS density and mass); 0 = the
-    # Riemann p* of Eq. (8) with each side's own state
+    # dummy (p* of Eq. (11), the light phase's EOS density and mass) with the
+    # heavy particle's pressure, 2 = the same with the pressure extrapolated
+    # from the heavy particle's light neighbours (Eq. (12) divided by rho_f);
+    # 0 = the Riemann p* of Eq. (8) with each side's own state
     cross_phase: int = 0
 
     @property

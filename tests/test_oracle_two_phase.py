@@ -379,3 +379,39 @@ def test_light_phase_sees_heavy_particles_as_wall_dummies(orc, dim):
                       np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
     assert np.array_equal(A0[:nh], A[:nh])
     assert np.abs(A0[nh:] - A[nh:]).max() > 1e-3 * np.abs(A[nh:]).max()  # the reading matters for the air
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_light_phase_sees_dummies_with_extrapolated_pressure(orc, dim):
+    # cross_phase = 2: each heavy particle carries, as the light phase's
+    # dummy, the pressure Eq. (12) (two-phase form) gives a wall particle at
+    # its place from the light particles alone.  An air particle's
+    # acceleration must equal the one it gets next to wall dummies at the
+    # water particles' places carrying exactly those wall pressures (viscosity
+    # and the wall penalty off, gravity on); the water's own accelerations do
+    # not change.
+    rng = np.random.default_rng(37)
+    dx, c = 0.01, 30.0
+    n = 10 if dim == 2 else 6
+    pts = lattice(dim, n, dx) + rng.normal(0, 0.05 * dx, (n ** dim, dim))
+    low = pts[:, -1] < 0.5 * n * dx
+    xh, xl = pts[low], pts[~low]
+    nh = len(xh)
+    v = rng.normal(0, 0.2, (len(pts), dim))
+    ph = rng.uniform(0.0, 400.0, nh)
+    pl = rng.uniform(0.0, 1.0, len(xl))
+    rho_h, rho_l = RHO_W + ph / c ** 2, RHO_A + pl / c ** 2
+    g = (0, -G, 0) if dim == 2 else (0, 0, -G)
+    kw = dict(dim=dim, dx=dx, h=1.3 * dx, rho0=RHO_W, c=c, dt=1e-4, g=g, gamma_p=0.0, penalty_on=False)
+    Pd = orc.params(n_heavy=nh, rho0_light=RHO_A, cross_phase=2, **kw)
+    A = orc.momentum(Pd, np.concatenate([xh, xl]), v, np.concatenate([rho_h, rho_l]),
+                     np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    Pw = orc.params(n_heavy=0, rho0_light=RHO_A, **kw)  # every fluid particle light, water as walls
+    pd = orc.wall_pressure(Pw, xh, xl, rho_l)            # Eq. (12) at the water particles from the air
+    assert np.abs(pd).max() > 0.0
+    Aw = orc.momentum(Pw, xl, v[nh:], rho_l, xh, pd, np.zeros((nh, dim)))
+    assert np.abs(A[nh:] - Aw).max() < 1e-12 * np.abs(Aw).max()
+    P0 = orc.params(n_heavy=nh, rho0_light=RHO_A, cross_phase=0, **kw)
+    A0 = orc.momentum(P0, np.concatenate([xh, xl]), v, np.concatenate([rho_h, rho_l]),
+                      np.zeros((0, dim)), np.zeros(0), np.zeros((0, dim)))
+    assert np.array_equal(A0[:nh], A[:nh])
