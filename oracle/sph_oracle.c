@@ -145,8 +145,8 @@ double orc_dW(int dim, double h, double r)
 }
 
 /* ------------------------------------------------------------------ */
-/* Neighbour search with a cell list (Sec. 3: "neighbour search        */
-/* (including sorting algorithms)").  A counting sort by cell key is    */
+/* Neighbour search with a cell list (Sec. 3; Table 1 counts the sort   */
+/* as part of the neighbour search).  A counting sort by cell key is    */
 /* stable: particles of one cell keep their input order.                */
 /* ------------------------------------------------------------------ */
 
