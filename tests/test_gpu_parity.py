@@ -320,6 +320,41 @@ def test_edge_coincident_particles(solver_mod):
     assert np.all(np.isfinite(e["acc"])) and np.all(np.isfinite(e["rho"]))
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_edge_mask_overflow_walks_the_cells(solver_mod, prec):
+    # A clump of 125 particles 0.3 dx apart inside one cell, on the floor of
+    # the box: every stencil row through that cell holds more than 128
+    # candidates (fluid queries, and the top wall layer's queries over the
+    # fluid), so those queries get count -1, are counted in the status and
+    # walk the cells in every sweep.  The run must equal, bit for bit, one that
+    # walks the cells throughout.
+    sc = SMALL["box3d"]()
+    g = np.arange(5) * 0.003
+    clump = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) + np.array([0.0755, 0.0755, 0.002])
+    x = np.concatenate([sc.fluid_x, clump])
+    v = np.concatenate([sc.fluid_v, np.zeros_like(clump)])
+    rho = np.concatenate([sc.fluid_rho, np.full(len(clump), sc.rho0)])
+    sc = sc.with_params(fluid_x=x, fluid_v=v, fluid_rho=rho)
+    a = solver_mod.Solver(sc, prec, lists=True)
+    b = solver_mod.Solver(sc, prec, lists=False)
+    # the clump sits inside one cell of the grid
+    L, lo = float(a.desc.cell), np.array(list(a.desc.lo))
+    cells = np.floor((clump - lo) / L).astype(int)
+    assert (cells == cells[0]).all()
+    a.step(3)
+    b.step(3)
+    raw = a.raw()
+    assert (raw["cnt_ff"] == -1).any() and (raw["cnt_wf"] == -1).any()
+    ea, eb = a.export(), b.export()
+    for k in ("pos", "vel", "rho", "acc"):
+        assert np.array_equal(ea[k], eb[k]), k
+    assert np.array_equal(a.export_walls()["pw"], b.export_walls()["pw"])
+    sa, sb = a.status(), b.status()
+    assert sa["list_overflow"] > 0 and sb["list_overflow"] == 0
+    assert {k: sa[k] for k in ("out_of_grid", "fast", "nonfinite")} == \
+        {k: sb[k] for k in ("out_of_grid", "fast", "nonfinite")} == dict(out_of_grid=0, fast=0, nonfinite=0)
+
+
 # ---------------------------------------------------------------- full size, sampled
 FULL = {
     "dam3d_dx0.004": lambda: scenes.dam_break_3d(dx=0.004),
