@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint/forward ratio")
     ap.add_argument("--sloshing-only", type=float, default=None, metavar="DX",
                     help="time only the shaken two-phase tank at this dx (kernel profiles of that case)")
+    ap.add_argument("--large-only", type=float, default=None, metavar="DX",
+                    help="time only the dam break with obstacles at this (small) dx: throughput and device "
+                         "memory of a large problem")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps of the CPU baseline (about 3 s each)")
     ap.add_argument("--cpu-stride", type=int, default=16,
@@ -267,6 +270,25 @@ def main():
                               value=ns * args.steps / walls_, unit="particle-steps/s",
                               ms_per_step=1e3 * walls_ / args.steps, steps=args.steps,
                               stage_ms={k: round(v, 4) for k, v in stages.items()}, status=Ss.status())),
+              flush=True)
+        return
+
+    if args.large_only:
+        t0 = time.perf_counter()
+        scl = scenes.dam_break_3d(dx=args.large_only, obstacles=args.obstacles, seed=0, steps=args.steps)
+        t_scene = time.perf_counter() - t0
+        print(f"[bench] large: {scl.n_fluid} fluid + {scl.n_wall} wall (scene {t_scene:.0f} s)", file=sys.stderr,
+              flush=True)
+        torch.cuda.reset_peak_memory_stats()
+        Sl, walll, stages = timed_run(solver, scl, "f32", args.steps, args.warmup)
+        nl = scl.n_fluid + scl.n_wall
+        print(json.dumps(dict(workload=f"3-D dam break with {args.obstacles} seeded obstacles, dx={args.large_only} m: "
+                                       f"{scl.n_fluid} fluid + {scl.n_wall} wall",
+                              value=nl * args.steps / walll, unit="particle-steps/s",
+                              ms_per_step=1e3 * walll / args.steps, steps=args.steps,
+                              stage_ms={k: round(v, 4) for k, v in stages.items()}, status=Sl.status(),
+                              device_gib=round(torch.cuda.max_memory_allocated() / 2 ** 30, 2),
+                              bytes_per_particle=round(torch.cuda.max_memory_allocated() / nl, 1))),
               flush=True)
         return
 
