@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--large-only", type=float, default=None, metavar="DX",
                     help="time only the dam break with obstacles at this (small) dx: throughput and device "
                          "memory of a large problem")
+    ap.add_argument("--penalty-off", action="store_true",
+                    help="the single-phase workloads without the wall penalty (the paper applies it to the light "
+                         "phase only): the cost of that term")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps of the CPU baseline (about 3 s each)")
     ap.add_argument("--cpu-stride", type=int, default=16,
@@ -293,6 +296,8 @@ def main():
         return
 
     sc = scenes.dam_break_3d(dx=args.dx, obstacles=args.obstacles, seed=0, steps=args.steps)
+    if args.penalty_off:
+        sc = sc.with_params(penalty_all=False)
     nf, nw = sc.n_fluid, sc.n_wall
     n_tot = nf + nw
     print(f"[bench] workload dam_break_3d dx={args.dx} obstacles={args.obstacles}: "
@@ -498,10 +503,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3-D dam break with 8 seeded obstacles, dx={args.dx} m, "
+        "config": {"workload": f"3-D dam break with {args.obstacles} seeded obstacles, dx={args.dx} m, "
                                f"{nf} fluid + {nw} wall dummy particles",
                    "n_fluid": nf, "n_wall": nw, "dx": args.dx, "obstacles": args.obstacles,
-                   "parallelism": "single GPU"},
+                   "wall_penalty": not args.penalty_off, "parallelism": "single GPU"},
         "fluid_particle_steps_per_s": nf * args.steps / wall,
         "fp32_4M": m4,
         "fp32_two_phase": tp,
