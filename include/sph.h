@@ -235,11 +235,11 @@ int sph_init(const sph_desc *desc, sph_buffers *buf, const double *fpos, const d
              const double *frho, const double *wpos, void *stream);
 
 /* Neighbour search with the sorting of particles by cell (Sec. 3, Table 1).
- * Stable counting sort of the drifted fluid (key[1], off[1], pid[1] and the
+ * Counting sort of the drifted fluid (key[1], off[1], pid[1] and the
  * current velocity and density) by cell key into key[0], off[0], pid[0] and
- * the other velocity/density copy; particles of one cell keep their prior
- * order.  Rebuilds fstart and, if present, the neighbour masks.  Swaps
- * sel_vel and sel_rho. */
+ * the other velocity/density copy; particles of one cell are ordered by
+ * their x offset, ties by their prior order.  Rebuilds fstart and, if
+ * present, the neighbour masks.  Swaps sel_vel and sel_rho. */
 int sph_build_cells(const sph_desc *desc, sph_buffers *buf, void *stream);
 
 /* Density update (Sec. 2.5 and 2.6): at the current positions

@@ -56,9 +56,9 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 //      cell is exact; the slot order inside a cell is arbitrary);
 //   2. exclusive scan of the counts -> cell start table;
 //   3. place: perm[start[key_i] + slot_i] = i;
-//   4. rank of each entry among its cell's entries by source index, which
-//      makes the order inside a cell the prior order: deterministic and
-//      stable;
+//   4. rank of each entry among its cell's entries: for the fluid by x
+//      offset, ties by source index, for the walls by source index (their
+//      prior order); deterministic either way;
 //   5. gather of every field through perm.
 // ---------------------------------------------------------------------------
 
@@ -179,21 +179,41 @@ __global__ void __launch_bounds__(kBlock) k_place(const int32_t* __restrict__ ke
     if (i < n) perm[start[key[i]] + slot[i]] = (int32_t)i;
 }
 
-// In-cell order by source index: each entry's rank among the entries of its
-// cell (the sources are distinct), so the permutation is that of a stable
-// counting sort whatever order the histogram atomics handed out slots in.
-// One thread per entry; the cell's few entries are read from cache.
+// In-cell order: each entry's rank among the entries of its cell by x
+// offset (ox), ties by source index, or by source index alone without ox;
+// either is a strict total order, so the permutation is the same whatever
+// order the histogram atomics handed out slots in.  The fluid is ordered by
+// x (the pair sweeps run faster on that order: the lanes of a cell then
+// find their neighbours at nearby record indices); the walls keep their
+// source order.  One thread per entry; the cell's few entries are read from
+// cache.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cellrank(const int32_t* __restrict__ key,
                                                       const int32_t* __restrict__ start,
                                                       const int32_t* __restrict__ placed, int64_t n,
-                                                      int32_t* __restrict__ perm) {
+                                                      const T* __restrict__ ox, int32_t* __restrict__ perm) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int v = placed[p];
     const int c = key[v];
     const int a = start[c], b = start[c + 1];
     int r = 0;
-    for (int q = a; q < b; ++q) r += placed[q] < v ? 1 : 0;
+    if (ox) {
+        const T xv = ox[v];
+        auto before = [&](int u, T xu) { return (xu < xv || (xu == xv && u < v)) ? 1 : 0; };
+        int q = a;
+        for (; q + 4 <= b; q += 4) {  // four independent index-then-offset loads in flight
+            const int u0 = placed[q], u1 = placed[q + 1], u2 = placed[q + 2], u3 = placed[q + 3];
+            const T x0 = ox[u0], x1 = ox[u1], x2 = ox[u2], x3 = ox[u3];
+            r += before(u0, x0) + before(u1, x1) + before(u2, x2) + before(u3, x3);
+        }
+        for (; q < b; ++q) {
+            const int u = placed[q];
+            r += before(u, ox[u]);
+        }
+    } else {
+        for (int q = a; q < b; ++q) r += placed[q] < v ? 1 : 0;
+    }
     perm[a + r] = v;
 }
 
@@ -1111,9 +1131,10 @@ __global__ void __launch_bounds__(kBlock)
 
 // Sort n keys into cell order: start table + permutation (scratch.perm).
 // The histogram's slot of each key goes to scratch.perm, the placement by
-// slot to scratch.slot, and the in-cell ranking back to scratch.perm.
+// slot to scratch.slot, and the in-cell ranking back to scratch.perm, by x
+// offset when ox (the set's x offsets, precision of d) is given.
 int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n, int32_t* start,
-              hipStream_t st) {
+              hipStream_t st, const void* ox = nullptr) {
     const int64_t nc = d->n_cells;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nc)), dim3(kBlock), 0, st, s.count, nc, 0);
     SPH_LAUNCH_CHECK();
@@ -1133,7 +1154,12 @@ int sort_keys(const sph_desc* d, const Scratch& s, const int32_t* key, int64_t n
         hipLaunchKernelGGL(k_place, dim3(grid_for(n)), dim3(kBlock), 0, st, key, s.perm, n, start,
                            s.slot);
         SPH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cellrank, dim3(grid_for(n)), dim3(kBlock), 0, st, key, start, s.slot, n, s.perm);
+        if (d->precision == SPH_F64)
+            hipLaunchKernelGGL(k_cellrank<double>, dim3(grid_for(n)), dim3(kBlock), 0, st, key, start, s.slot, n,
+                               (const double*)ox, s.perm);
+        else
+            hipLaunchKernelGGL(k_cellrank<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, key, start, s.slot, n,
+                               (const float*)ox, s.perm);
         SPH_LAUNCH_CHECK();
     }
     return SPH_OK;
@@ -1143,7 +1169,7 @@ template <typename T, int D>
 int build_cells_t(const sph_desc* d, sph_buffers* b, hipStream_t st) {
     const Scratch s = layout(d, b->n_fluid, b->n_wall, b->scratch);
     const int64_t n = b->n_fluid;
-    int rc = sort_keys(d, s, b->key[1], n, b->fstart, st);
+    int rc = sort_keys(d, s, b->key[1], n, b->fstart, st, b->off[1]);
     if (rc) return rc;
     if (n > 0) {
         const int sv = b->sel_vel, sr = b->sel_rho;

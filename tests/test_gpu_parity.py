@@ -51,10 +51,15 @@ def test_pair_sets_and_sort_bitexact(solver_mod, name, prec):
     assert np.array_equal(raw["fstart"], np.concatenate([[0], np.cumsum(cnt)]))
     wcnt = np.bincount(raw["wkey"], minlength=int(S.desc.n_cells))
     assert np.array_equal(raw["wstart"], np.concatenate([[0], np.cumsum(wcnt)]))
-    # stable: from the input order (ids ascending) a stable sort keeps ids
-    # ascending inside each cell
-    start, order = O.counting_sort(key[np.argsort(raw["pid"][0])], int(S.desc.n_cells))
-    assert np.array_equal(raw["pid"][0], order)
+    # fluid order: by cell key, inside a cell by x offset (as stored, in the
+    # kernel precision), ties by prior index (the input order: ids ascending)
+    pid = raw["pid"][0]
+    key_id = np.empty_like(key)
+    key_id[pid] = key
+    x_id = np.empty(nf, dtype=raw["off"][0].dtype)
+    x_id[pid] = raw["off"][0][0]
+    assert np.array_equal(pid, np.lexsort((np.arange(nf), x_id, key_id)))
+    # walls: by cell key, ties by source index (a stable counting sort)
     assert np.array_equal(raw["wpid"], O.counting_sort(raw["wkey"][np.argsort(raw["wpid"])],
                                                        int(S.desc.n_cells))[1])
     # pair sets in the kernel's precision
@@ -129,10 +134,12 @@ def test_stage_parity(solver_mod, name, prec):
     errs["v_half"] = scaled(vh, vh_o, sc_["v"])
     x1 = by_pid(raw["pid"][1], S.absolute(raw["key"][1], raw["off"][1]))
     errs["x1"] = scaled(x1, x0 + sc.dt * vh, sc_["x"])
-    # cell build: a stable counting sort of the drifted keys in their prior order
+    # cell build: the drifted keys sorted, inside each cell by x offset, ties
+    # by prior order
     S.build_cells()
     raw2 = S.raw()
-    _, order = O.counting_sort(raw["key"][1], int(S.desc.n_cells))
+    n1 = len(raw["key"][1])
+    order = np.lexsort((np.arange(n1), raw["off"][1][0], raw["key"][1]))
     assert np.array_equal(raw2["pid"][0], raw["pid"][1][order])
     assert np.array_equal(raw2["key"][0], raw["key"][1][order])
     e1 = S.export()
