@@ -11,6 +11,9 @@
   (nothing left the grid, moved more than a cell per step, turned
   non-finite or overflowed its masks), exact mass, and the FP32-FP64 drift
   of positions, velocities, pressure and energy printed.
+* The dam break with obstacles at dx = 0.00095 m (126M fluid + 13M wall,
+  where the neighbour-mask offsets pass 2^31): sampled neighbour counts
+  exact against the oracle's pair test and one step's fields within 1e-4.
 
 Scales: x -> dx, v -> sqrt(2 g H), p and p_w -> rho0 g H, dv/dt -> g.
 """
@@ -125,3 +128,82 @@ def test_long_run_clean_status_and_fp32_drift(solver_mod, name):
     # the particles stay within a fraction of a spacing in the mean
     assert abs(E32 - E64) <= 1e-3 * abs(E64)
     assert math.sqrt(np.mean(dx_ ** 2)) < 0.1
+
+
+def test_largest_size_sampled_parity(solver_mod):
+    # The 3-D dam break with obstacles at dx = 0.00095 m: about 126M fluid
+    # and 13M wall particles, where the neighbour-mask offsets (stencil row x
+    # word x particles) pass 2^31.  One step in, then one step stage by stage,
+    # on sampled particles that the oracle evaluates one by one: each sampled
+    # particle's neighbour count from the masks equals the oracle's pair test
+    # in the kernel's precision, and every stage's fields are within 1e-4.
+    sc = scenes.dam_break_3d(dx=0.00095, obstacles=8, seed=0)
+    nf, nw = sc.n_fluid, sc.n_wall
+    assert 18 * nf > 2 ** 31
+    print(f"[largest] nf={nf} nw={nw}", flush=True)
+    s = scales(sc)
+    S = solver_mod.Solver(sc, "f32")
+    S.step(1)
+    print("  stepped", flush=True)
+    P = O.params_from_scene(sc)
+    rng = np.random.default_rng(11)
+    e0 = S.export()
+    x0 = e0["pos"]
+    w0 = S.export_walls()
+    wx, wn = w0["pos"], w0["nrm"]
+    near_wall = np.nonzero(x0[:, 2] < 3 * sc.dx)[0]
+    qf = np.unique(np.concatenate([rng.choice(nf, 2000, replace=False),
+                                   rng.choice(near_wall, min(500, len(near_wall)), replace=False)]))
+    qw = rng.choice(nw, 1000, replace=False)
+    # neighbour counts of the sampled particles against the oracle's pair
+    # test in FP32 cell + offset over its FP64 candidates within 2h (1 + 1e-5)
+    raw = S.raw()
+    pid, wpid = raw["pid"][0], raw["wpid"]
+    inv_f = np.empty(nf, dtype=np.int64)
+    inv_f[pid] = np.arange(nf)
+    inv_w = np.empty(nw, dtype=np.int64)
+    inv_w[wpid] = np.arange(nw)
+    cnt = (raw["cnt_ff"] + raw["cnt_fw"])[inv_f[qf]]
+    assert (raw["cnt_ff"] >= 0).all() and (raw["cnt_fw"] >= 0).all()
+    L = float(S.desc.cell)
+    rc2 = float(np.float32(4.0 * sc.h * sc.h))
+    ocnt, olst = O.neighbours(sc.dim, sc.h * (1 + 1e-5), x0[qf], np.concatenate([x0, wx]))
+    oo = np.concatenate([[0], np.cumsum(ocnt)])
+    for a, i in enumerate(qf):
+        cand = olst[oo[a]:oo[a + 1]].astype(np.int64)
+        srt = np.where(cand < nf, inv_f[np.minimum(cand, nf - 1)], inv_w[np.maximum(cand - nf, 0)])
+        isw = cand >= nf
+        cc = np.where(isw[:, None], S.cell_coords(raw["wkey"][srt * isw]), S.cell_coords(raw["key"][0][srt * ~isw]))
+        oc = np.where(isw[:, None], raw["woff"].T[srt * isw], raw["off"][0].T[srt * ~isw]).astype(np.float64)
+        si = inv_f[i]
+        ci = S.cell_coords(raw["key"][0][[si]])
+        oi = raw["off"][0].T[[si]].astype(np.float64)
+        hit = O.pairs_bruteforce(sc.dim, True, ci, oi, cc, oc, L, rc2)[0]
+        assert int(hit.sum()) == int(cnt[a]), (i, int(hit.sum()), int(cnt[a]))
+    del raw
+    print(f"  {len(qf)} sampled neighbour counts exact", flush=True)
+    # one step stage by stage
+    S.density()
+    e_mid = S.export()
+    sig_o = O.sigma(P, x0, wx, query=qf)
+    rt_o = O.reinit(P, sig_o, e0["rho"][qf])
+    errs = dict(p_reinit=float(np.abs(sc.c0 ** 2 * (e_mid["rho"][qf] - rt_o)).max() / s["p"]),
+                v_half=float(np.abs(e_mid["vel"][qf] - (e0["vel"][qf] + 0.5 * sc.dt * e0["acc"][qf])).max() / s["v"]))
+    del e_mid, e0
+    S.build_cells()
+    e1 = S.export()
+    S.wall_bc()
+    pw1 = S.export_walls()["pw"]
+    errs["pw"] = float(np.abs(pw1[qw] - O.wall_pressure(P, wx, e1["pos"], e1["rho"], query=qw)).max() / s["p"])
+    S.continuity()
+    rho2 = S.export()["rho"]
+    D_o = O.continuity(P, e1["pos"], e1["vel"], e1["rho"], wx, pw1, query=qf)
+    errs["p_new"] = float(np.abs(sc.c0 ** 2 * (rho2[qf] - (e1["rho"][qf] + sc.dt * D_o))).max() / s["p"])
+    S.momentum()
+    e3 = S.export()
+    A_o = O.momentum(P, e1["pos"], e1["vel"], rho2, wx, pw1, wn, query=qf)
+    errs["acc"] = float(np.abs(e3["acc"][qf] - A_o).max() / max(G, np.abs(A_o).max()))
+    print("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), S.status(), flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= 1e-4}
+    assert not bad, bad
+    assert S.status() == CLEAN
